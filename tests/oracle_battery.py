@@ -1,0 +1,93 @@
+"""A fast battery of oracle pins, runnable against any build of the oracle C file.
+
+Used by ``test_oracle_mutants.py``: each planted mistake in a copy of the oracle
+must make at least one of these checks fail.  Every reference here is
+independent of the oracle's own arithmetic (LAPACK eigen-decomposition,
+numpy's Gauss-Legendre rule, a complex-step Jacobian, the numerical-eigensolver
+DOT scheme, closed-form path integrals).
+
+Run as ``python oracle_battery.py <liboracle.so>``; exit status 0 iff all pass.
+"""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle import dot_numeric  # noqa: E402
+from paper_1912_04791_amd import inputs  # noqa: E402
+
+G = 9.81
+
+
+def checks(lib):
+    out = {}
+    rng = np.random.default_rng(0)
+    n = 200
+    h = rng.uniform(0.1, 4.0, n)
+    u = rng.uniform(-2.5, 2.5, n)
+    q = h * u
+    z = rng.uniform(-1, 1, n)
+    xi, Ag = 1.0 / 0.6, 0.02
+
+    e = oracle.eigensystem(h, q, z, G, xi, Ag, lib=lib, check=False)
+    A_ind = dot_numeric.flux_matrix(h, q, G, xi, Ag)
+    out["flux_matrix"] = np.max(np.abs(e["A"] - A_ind)) <= 1e-13 * np.abs(A_ind).max()
+    lam_ref = np.sort(np.linalg.eigvals(A_ind).real, axis=1)
+    out["eigenvalues"] = bool(np.all(np.abs(e["lam"] - lam_ref)
+                                     <= 1e-12 * np.abs(lam_ref).max(axis=1, keepdims=True)))
+    Ar = A_ind @ e["R"]
+    lr = e["R"] * e["lam"][:, None, :]
+    out["right_vectors"] = bool(np.max(np.abs(Ar - lr)) <= 1e-10 * np.abs(Ar).max())
+    lA = e["Rinv"] @ A_ind
+    ll = e["Rinv"] * e["lam"][:, :, None]
+    out["left_vectors"] = bool(np.max(np.abs(lA - ll)) <= 1e-10 * np.abs(lA).max())
+    aref = dot_numeric.abs_matrix(A_ind)
+    out["abs_matrix"] = bool(np.max(np.abs(e["absA"] - aref)) <= 1e-11 * np.abs(aref).max())
+
+    s, w = oracle.gauss(3, lib=lib)
+    x, wl = np.polynomial.legendre.leggauss(3)
+    out["gauss"] = bool(np.allclose(s, 0.5 * (x + 1), atol=1e-15) and
+                        np.allclose(w, 0.5 * wl, atol=1e-15))
+
+    WL, WR = inputs.make_random_edges(300, seed=3)
+    Dm, Dp = oracle.fluct(WL, WR, G, xi, Ag, G=3, nthreads=2, lib=lib, check=False)
+    rm, rp = dot_numeric.fluct(np.array(WL), np.array(WR), G, xi, Ag, G=3)
+    sc = np.abs(rm).max() + np.abs(rp).max()
+    out["fluct"] = bool(np.max(np.abs(Dm - rm)) <= 1e-11 * sc and
+                        np.max(np.abs(Dp - rp)) <= 1e-11 * sc)
+
+    for name, wl, periodic in (("scheme_c1", inputs.make_c1(n_cells=120, steps=25), False),
+                               ("scheme_periodic", inputs.make_c2(n_cells=256, steps=25), True)):
+        xi_c = 1.0 / (1.0 - wl.porosity[0])
+        spec = oracle.ChannelSpec(n_cells=wl.n_cells, dx=float(wl.dx[0]), Ag=float(wl.Ag[0]),
+                                  porosity=float(wl.porosity[0]), bc_left=int(wl.bc_left[0]),
+                                  bc_right=int(wl.bc_right[0]))
+        try:
+            hh, qq, zz, t = oracle.run(spec, wl.h, wl.q, wl.z, wl.steps, nthreads=2, lib=lib)
+        except oracle.OracleError:
+            out[name] = False
+            continue
+        hn, qn, zn, tn = dot_numeric.run(wl.h, wl.q, wl.z, wl.steps, wl.dx[0], G, xi_c, wl.Ag[0],
+                                         cfl=wl.cfl, periodic=periodic)
+        ok = abs(t - tn) <= 1e-12 * tn
+        for a, r in ((hh, hn), (qq, qn), (zz, zn)):
+            ok = ok and np.abs(a - r).sum() <= 1e-12 * max(np.abs(r).sum(), 1e-3 * np.abs(hn).sum())
+        out[name] = bool(ok)
+    return out
+
+
+def main(path):
+    lib = oracle._load(path)
+    res = checks(lib)
+    failed = [k for k, v in res.items() if not v]
+    print("failed:", failed if failed else "none")
+    return 1 if failed else 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1]))
