@@ -1,0 +1,192 @@
+/*
+ * dsve.h -- C ABI of libdsve.so: the A-DOT hot path for the 1-D de Saint
+ * Venant-Exner system on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Carraro, Valiani, Caleffi, "Efficient analytical implementation of
+ * the DOT Riemann solver for the de Saint Venant-Exner morphodynamic model"):
+ *   state per cell W = (h, q, z): water depth, unit discharge, bed elevation
+ *   (Sec. 2, Eq. W&A_definition); Grass bed load q_s = A_g u^3 (Sec. 2, Eq. Grass);
+ *   DOT fluctuations D^{+-} = 1/2 sum_k w_k (A(Psi_k) +- |A(Psi_k)|)(W+ - W-)
+ *   on the segment path with a G-point Gauss-Legendre rule (Sec. 3.1, Eqs. path,
+ *   DOTjumpN), |A| = R |Lambda| R^-1 from the closed-form eigenstructure
+ *   (Sec. 3.3, Eqs. lambda, parameters, RR, RR-1, ExAbsA); first-order update
+ *   W_i <- W_i - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) with no source term
+ *   (Sec. 3, Eq. scheme; friction neglected as in Sec. 4);
+ *   dt = CFL dx / max_i max_m |lambda_m(W_i)|.
+ *
+ * Conventions shared by every entry point:
+ *   - All state, fluctuation and time arrays are DEVICE pointers to float64
+ *     (both precisions keep FP64 state in memory).  The caller owns them; the
+ *     library never frees or reallocates them.
+ *   - States are structure-of-arrays: h[i], q[i], z[i] for cell i.  Several
+ *     channels are stored back to back; channel c owns cells [off[c], off[c+1]).
+ *   - Edge e of a channel of N cells lies between cell e-1 and cell e, e = 0..N;
+ *     cells -1 and N are the ghost cells given by the boundary conditions.
+ *     Fluctuation arrays are [3][n] with component r of edge e at r*n + e.
+ *   - Work is enqueued on the HIP stream given at init (NULL = the null stream)
+ *     and returns without waiting.  Errors raised on the device (a non-finite
+ *     CFL speed, complex eigenvalues) are deferred: dsve_sync() waits and
+ *     reports them.  A failed call leaves its message in dsve_last_error().
+ *     Errors are sticky per context until dsve_clear_error().
+ *   - One context per stream; contexts share no state.  Calls that overlap on
+ *     the same context from several host threads are not supported.
+ */
+#ifndef DSVE_H
+#define DSVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSVE_ABI_VERSION 1
+
+typedef struct dsve_ctx dsve_ctx;
+
+typedef enum {
+    DSVE_OK = 0,
+    DSVE_E_ARG = -1,            /* invalid argument (null pointer, size, parameter range) */
+    DSVE_E_HIP = -2,            /* a HIP runtime call failed */
+    DSVE_E_NONFINITE = -3,      /* a CFL speed was NaN/Inf or zero (e.g. h <= 0, coalescing roots) */
+    DSVE_E_NONHYPERBOLIC = -4,  /* arccos argument outside [-1-1e-12, 1+1e-12] or k1 <= 0 */
+    DSVE_E_UNSUPPORTED = -5     /* valid but not implemented (e.g. another bed-load law) */
+} dsve_status;
+
+enum { DSVE_BC_TRANSMISSIVE = 0, DSVE_BC_PERIODIC = 1, DSVE_BC_INFLOW_Q = 2 };
+enum { DSVE_LAW_GRASS = 0 };
+enum { DSVE_FP64 = 0, DSVE_MIXED = 1 };
+
+/* Parameters common to a context.
+ *   g          gravitational acceleration (> 0)
+ *   porosity   bed porosity p in [0, 1); xi = 1/(1-p)  (Sec. 2)
+ *   law        DSVE_LAW_GRASS (q_s = A_g u^3, Sec. 2 Eq. Grass)
+ *   A_g        Grass coefficient (>= 0)
+ *   law_extra  reserved for further closures, must be zero
+ *   n_gauss    quadrature points G in [1, 5] (Sec. 3.1 Eq. DOTjumpN); 3 is the default
+ *   cfl        Courant number in (0, 1]
+ *   dx         cell width (> 0)
+ *   bc_left, bc_right   DSVE_BC_*; periodic must be set on both sides
+ *   q_in       unit discharge imposed by DSVE_BC_INFLOW_Q (ghost = (h_adjacent, q_in, z_adjacent))
+ *   precision  DSVE_FP64: all arithmetic in FP64.
+ *              DSVE_MIXED: eigenstructure and quadrature in FP32; FP64 for the
+ *              jumps W+ - W-, for the cubic's root solve and the eigenvector
+ *              normalisation where the arccos argument is close to +-1
+ *              (coalescing eigenvalues), and for the cell accumulation. */
+typedef struct {
+    double g;
+    double porosity;
+    int law;
+    double A_g;
+    double law_extra[4];
+    int n_gauss;
+    double cfl;
+    double dx;
+    int bc_left, bc_right;
+    double q_in;
+    int precision;
+} dsve_params;
+
+/* Library ABI version (DSVE_ABI_VERSION). */
+int dsve_abi_version(void);
+
+/* Create a context for one channel of n_cells cells (n_cells >= 1).
+ * Allocates device scratch: one ping-pong copy of the state (24 B per cell),
+ * fluctuation scratch is not allocated.  hip_stream is a hipStream_t or NULL.
+ * On error *out is NULL and the status says why (no context to query). */
+dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, void *hip_stream);
+
+/* Create a context for n_channels independent channels (n_channels >= 1).
+ * HOST arrays, all of length n_channels unless stated:
+ *   offsets[n_channels+1]  cell offsets, offsets[0] = 0, strictly increasing
+ *   A_g, porosity, dx      per-channel parameters (ranges as in dsve_params)
+ *   bc_left, bc_right      per-channel boundary conditions
+ *   q_in                   per-channel inflow discharge (may be NULL: zero)
+ * Everything else (g, law, n_gauss, cfl, precision) comes from *common; the
+ * per-channel fields of *common (A_g, porosity, dx, bc_*, q_in) are ignored.
+ * Each channel gets its own time step and clock (Sec. 3, Eq. scheme per channel). */
+dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *offsets,
+                            const double *A_g, const double *porosity, const double *dx,
+                            const int *bc_left, const int *bc_right, const double *q_in,
+                            const dsve_params *common, void *hip_stream);
+
+/* Release the context and its device scratch (waits for its queued work). */
+dsve_status dsve_destroy(dsve_ctx *ctx);
+
+/* Pairwise DOT fluctuations of n independent edges (Sec. 3.1, Eq. DOTjumpN with
+ * the segment path Eq. path; |A| from Sec. 3.3).  Left states (hL, qL, zL) and
+ * right states (hR, qR, zR) are device arrays of n doubles; Dm and Dp receive
+ * D^- and D^+ as [3][n] device arrays.  Uses the context's g, porosity, A_g,
+ * n_gauss and precision (for a batched context: those of channel 0). */
+dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, const double *zL,
+                           const double *hR, const double *qR, const double *zR, int64_t n,
+                           double *Dm, double *Dp);
+
+/* Cell update of one channel (Sec. 3, Eq. scheme, S = 0): for i = 0..N-1,
+ *   W_i <- W_i - (dt/dx) (Dm[:, i+1] + Dp[:, i])
+ * with Dm, Dp the [3][N+1] edge fluctuations (edge i is the left face of cell i),
+ * dt_dev a device pointer to the time step, and h, q, z updated in place.
+ * Single-channel contexts only. */
+dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const double *dt_dev,
+                        double *h, double *q, double *z);
+
+/* CFL reduction of one channel: *amax_dev = max_i max_m |lambda_m(W_i)| over the
+ * N real cells (eigenvalues of Sec. 3.3, Eq. lambda) and *dt_dev = cfl*dx/amax.
+ * amax_dev and dt_dev are device pointers to one double each.  The maximum is
+ * exact (order independent); a NaN speed wins it and is reported by dsve_sync.
+ * Single-channel contexts only. */
+dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const double *z,
+                       double *amax_dev, double *dt_dev);
+
+/* Advance one channel by n_steps >= 0 time steps in place: per step, ghost
+ * cells from the boundary conditions, dt = cfl*dx/amax(W^n), DOT fluctuations
+ * at every edge, cell update, and the CFL speed of W^{n+1} for the next step --
+ * one fused kernel per step, replayed from a HIP graph.  *t_dev (device) is
+ * increased by the sum of the time steps.  The result is in (h, q, z) when the
+ * enqueued work completes, bitwise independent of the launch configuration. */
+dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps, double *t_dev);
+
+/* As adot_step for a batched context: h, q, z hold all channels back to back
+ * (offsets as given to dsve_batch_init); t_dev[n_channels] receives each
+ * channel's clock.  All channels run in one persistent kernel per step. */
+dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                              double *t_dev);
+
+/* Wait for the context's queued work; report a deferred device error
+ * (DSVE_E_NONFINITE, DSVE_E_NONHYPERBOLIC) raised since the last sync. */
+dsve_status dsve_sync(dsve_ctx *ctx);
+
+/* Message of the last error on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char *dsve_last_error(const dsve_ctx *ctx);
+
+/* Clear the sticky error state. */
+dsve_status dsve_clear_error(dsve_ctx *ctx);
+
+/* Launch configuration of the fused step kernel.
+ *   tile           threads (= edges) per workgroup: 64, 128 or 256
+ *   blocks_per_cu  persistent workgroups per compute unit (1..32); 0 = one
+ *                  workgroup per tile (no persistence)
+ *   graph_steps    steps per captured HIP graph: a multiple of 6 in [6, 600],
+ *                  or 0 to launch every step directly
+ * The results do not depend on these (each edge and cell is computed the same
+ * way whatever tile it falls in). */
+dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int graph_steps);
+dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, int *graph_steps);
+
+/* Autotuner: time candidate (tile, blocks_per_cu) pairs for `trial_steps`
+ * fused steps each on a scratch copy of (h, q, z) -- the caller's arrays are
+ * read, never written -- and keep the fastest in the context.  If cache_path is
+ * not NULL, a JSON cache keyed by device, precision and problem shape is read
+ * first and updated after tuning.  Waits for completion. */
+dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
+                          int trial_steps, const char *cache_path);
+
+/* Number of compute units of the context's device. */
+int dsve_device_cus(const dsve_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSVE_H */

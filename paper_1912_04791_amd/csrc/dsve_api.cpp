@@ -1,0 +1,695 @@
+// dsve_api.cpp -- host side of libdsve.so: the C ABI declared in include/dsve.h.
+//
+// A context owns: per-channel records and edge offsets on the device, the tile table of the
+// fused step kernel, one ping-pong copy of the state, three rotating CFL-maximum slots per
+// channel, a flag word for deferred device errors, and a cached HIP graph of `graph_steps`
+// fused steps.  A run of n steps is: clear slots -> CFL max of W^0 into slot 0 -> graph
+// replays (each node is one step kernel; slot and ping-pong phase repeat every 6 steps, so
+// graph_steps is a multiple of 6) -> leftover steps launched directly -> copy back when n is odd.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/dsve.h"
+#include "dsve_internal.hpp"
+
+using namespace dsve;
+
+struct dsve_ctx {
+    int device = 0;
+    int cus = 0;
+    std::string arch;
+    hipStream_t stream = nullptr;     // caller's stream (may be null)
+    hipStream_t cap_stream = nullptr; // private stream used only for graph capture
+    bool batched = false;
+
+    int precision = DSVE_FP64;
+    int G = 3;
+    double g = 9.81;
+    double cfl = 0.9;
+
+    int64_t n_channels = 0, n_cells = 0, n_edges = 0;
+    std::vector<ChanInfo> h_ch;
+    std::vector<int64_t> h_off, h_eoff;
+    ChanInfo *d_ch = nullptr;
+    int64_t *d_off = nullptr, *d_eoff = nullptr;
+    GaussRule rule{};
+
+    double *pp_h = nullptr, *pp_q = nullptr, *pp_z = nullptr;   // ping-pong copy
+    unsigned long long *d_amax = nullptr;                        // [3][C]
+    unsigned int *d_flags = nullptr;                             // [4]
+
+    int tile = 256, blocks_per_cu = 0, graph_steps = 60;
+    int32_t *d_tile_chan = nullptr;
+    int64_t n_tiles = 0;
+    int table_tile = 0;
+
+    hipGraphExec_t gexec = nullptr;
+    const void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    int g_steps = 0, g_tile = 0, g_grid = 0;
+
+    int last_amax_slot = -1;   // slot holding the CFL max of the latest state, or -1
+    dsve_status sticky = DSVE_OK;
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+static dsve_status fail(dsve_ctx *c, dsve_status st, const std::string &msg)
+{
+    if (c) {
+        if (c->sticky == DSVE_OK) c->sticky = st;
+        c->err = msg;
+    }
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e__ = (expr);                                                             \
+        if (e__ != hipSuccess)                                                               \
+            return fail((ctx), DSVE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+    } while (0)
+
+// Gauss-Legendre rules on [0, 1] from the closed forms of the Legendre roots for G <= 5
+// (nodes x in [-1, 1] mapped by s = (1 + x)/2, weights halved so they sum to one).
+static bool gauss_rule(int G, GaussRule &r)
+{
+    double x[5] = {0, 0, 0, 0, 0}, w[5] = {0, 0, 0, 0, 0};
+    switch (G) {
+    case 1: x[0] = 0.0; w[0] = 2.0; break;
+    case 2: x[0] = -1.0 / std::sqrt(3.0); x[1] = -x[0]; w[0] = w[1] = 1.0; break;
+    case 3:
+        x[0] = -std::sqrt(3.0 / 5.0); x[1] = 0.0; x[2] = -x[0];
+        w[0] = w[2] = 5.0 / 9.0; w[1] = 8.0 / 9.0;
+        break;
+    case 4: {
+        const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+        const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+        x[0] = -b; x[1] = -a; x[2] = a; x[3] = b;
+        w[0] = w[3] = (18.0 - std::sqrt(30.0)) / 36.0;
+        w[1] = w[2] = (18.0 + std::sqrt(30.0)) / 36.0;
+        break;
+    }
+    case 5: {
+        const double a = std::sqrt(5.0 - 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+        const double b = std::sqrt(5.0 + 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+        x[0] = -b; x[1] = -a; x[2] = 0.0; x[3] = a; x[4] = b;
+        w[0] = w[4] = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+        w[1] = w[3] = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
+        w[2] = 128.0 / 225.0;
+        break;
+    }
+    default: return false;
+    }
+    for (int k = 0; k < kMaxGauss; ++k) {
+        r.s[k] = (k < G) ? 0.5 * (1.0 + x[k]) : 0.0;
+        r.w[k] = (k < G) ? 0.5 * w[k] : 0.0;
+    }
+    return true;
+}
+
+static bool valid_bc(int b) { return b == DSVE_BC_TRANSMISSIVE || b == DSVE_BC_PERIODIC || b == DSVE_BC_INFLOW_Q; }
+
+static dsve_status check_common(const dsve_params *p, std::string &msg)
+{
+    if (!p) { msg = "params is NULL"; return DSVE_E_ARG; }
+    if (!(p->g > 0.0) || !std::isfinite(p->g)) { msg = "g must be > 0"; return DSVE_E_ARG; }
+    if (p->law != DSVE_LAW_GRASS) { msg = "only the Grass law is implemented"; return DSVE_E_UNSUPPORTED; }
+    for (double v : p->law_extra)
+        if (v != 0.0) { msg = "law_extra must be zero for the Grass law"; return DSVE_E_ARG; }
+    if (p->n_gauss < 1 || p->n_gauss > 5) { msg = "n_gauss must be in [1, 5]"; return DSVE_E_ARG; }
+    if (!(p->cfl > 0.0 && p->cfl <= 1.0)) { msg = "cfl must be in (0, 1]"; return DSVE_E_ARG; }
+    if (p->precision != DSVE_FP64 && p->precision != DSVE_MIXED) { msg = "unknown precision"; return DSVE_E_ARG; }
+    return DSVE_OK;
+}
+
+static dsve_status check_channel(double Ag, double por, double dx, int bcl, int bcr, double q_in,
+                                 std::string &msg)
+{
+    if (!(Ag >= 0.0) || !std::isfinite(Ag)) { msg = "A_g must be finite and >= 0"; return DSVE_E_ARG; }
+    if (!(por >= 0.0 && por < 1.0)) { msg = "porosity must be in [0, 1)"; return DSVE_E_ARG; }
+    if (!(dx > 0.0) || !std::isfinite(dx)) { msg = "dx must be > 0"; return DSVE_E_ARG; }
+    if (!valid_bc(bcl) || !valid_bc(bcr)) { msg = "unknown boundary condition"; return DSVE_E_ARG; }
+    if ((bcl == DSVE_BC_PERIODIC) != (bcr == DSVE_BC_PERIODIC)) { msg = "periodic must be set on both sides"; return DSVE_E_ARG; }
+    if (!std::isfinite(q_in)) { msg = "q_in must be finite"; return DSVE_E_ARG; }
+    return DSVE_OK;
+}
+
+static void free_graph(dsve_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_steps = 0;
+}
+
+static dsve_status build_tile_table(dsve_ctx *c, int tile)
+{
+    if (c->d_tile_chan && c->table_tile == tile) return DSVE_OK;
+    const int64_t span = tile - 1;
+    const int64_t nt = std::max<int64_t>(1, (c->n_edges - 1 + span - 1) / span);
+    std::vector<int32_t> tab(nt);
+    int64_t ch = 0;
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t g0 = k * span;
+        while (ch + 1 < c->n_channels && g0 >= c->h_eoff[ch + 1]) ++ch;
+        tab[k] = (int32_t)ch;
+    }
+    if (c->d_tile_chan) (void)hipFree(c->d_tile_chan);
+    c->d_tile_chan = nullptr;
+    HIP_TRY(c, hipMalloc(&c->d_tile_chan, sizeof(int32_t) * nt));
+    HIP_TRY(c, hipMemcpy(c->d_tile_chan, tab.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+    c->n_tiles = nt;
+    c->table_tile = tile;
+    free_graph(c);
+    return DSVE_OK;
+}
+
+static dsve_status setup(dsve_ctx *c, void *stream)
+{
+    HIP_TRY(c, hipGetDevice(&c->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    c->cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    c->stream = (hipStream_t)stream;
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    gauss_rule(c->G, c->rule);
+
+    const int64_t C = c->n_channels;
+    c->h_eoff.resize(C + 1);
+    for (int64_t k = 0; k <= C; ++k) c->h_eoff[k] = c->h_off[k] + k;
+    c->n_edges = c->h_eoff[C];
+    HIP_TRY(c, hipMalloc(&c->d_ch, sizeof(ChanInfo) * C));
+    HIP_TRY(c, hipMalloc(&c->d_off, sizeof(int64_t) * (C + 1)));
+    HIP_TRY(c, hipMalloc(&c->d_eoff, sizeof(int64_t) * (C + 1)));
+    HIP_TRY(c, hipMemcpy(c->d_ch, c->h_ch.data(), sizeof(ChanInfo) * C, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_off, c->h_off.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_eoff, c->h_eoff.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMalloc(&c->pp_h, sizeof(double) * c->n_cells));
+    HIP_TRY(c, hipMalloc(&c->pp_q, sizeof(double) * c->n_cells));
+    HIP_TRY(c, hipMalloc(&c->pp_z, sizeof(double) * c->n_cells));
+    HIP_TRY(c, hipMalloc(&c->d_amax, sizeof(unsigned long long) * 3 * C));
+    HIP_TRY(c, hipMalloc(&c->d_flags, sizeof(unsigned int) * 4));
+    HIP_TRY(c, launch_fill_u64(c->d_amax, 3 * C, 0ull, c->stream));
+    HIP_TRY(c, launch_fill_u32(c->d_flags, 4, 0u, c->stream));
+    dsve_status st = build_tile_table(c, c->tile);
+    if (st != DSVE_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DSVE_OK;
+}
+
+static void release(dsve_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_graph(c);
+    (void)hipFree(c->d_ch);
+    (void)hipFree(c->d_off);
+    (void)hipFree(c->d_eoff);
+    (void)hipFree(c->pp_h);
+    (void)hipFree(c->pp_q);
+    (void)hipFree(c->pp_z);
+    (void)hipFree(c->d_amax);
+    (void)hipFree(c->d_flags);
+    (void)hipFree(c->d_tile_chan);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+static ChanInfo make_chan(int64_t cell0, int64_t n, double Ag, double por, double dx, int bcl,
+                          int bcr, double q_in, double cfl)
+{
+    ChanInfo ci{};
+    ci.cell0 = cell0;
+    ci.ncell = n;
+    const double xi = 1.0 / (1.0 - por);
+    ci.kq = 3.0 * xi * Ag;
+    ci.cfl_dx = cfl * dx;
+    ci.dx = dx;
+    ci.q_in = q_in;
+    ci.bcl = bcl;
+    ci.bcr = bcr;
+    return ci;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int dsve_abi_version(void) { return DSVE_ABI_VERSION; }
+
+dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, void *hip_stream)
+{
+    if (!out) return DSVE_E_ARG;
+    *out = nullptr;
+    std::string msg;
+    dsve_status st = check_common(p, msg);
+    if (st != DSVE_OK) return st;
+    if (n_cells < 1) return DSVE_E_ARG;
+    st = check_channel(p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right, p->q_in, msg);
+    if (st != DSVE_OK) return st;
+    dsve_ctx *c = new dsve_ctx();
+    c->precision = p->precision;
+    c->G = p->n_gauss;
+    c->g = p->g;
+    c->cfl = p->cfl;
+    c->n_channels = 1;
+    c->n_cells = n_cells;
+    c->h_off = {0, n_cells};
+    c->h_ch.push_back(make_chan(0, n_cells, p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right,
+                                p->q_in, p->cfl));
+    st = setup(c, hip_stream);
+    if (st != DSVE_OK) {
+        release(c);
+        return st;
+    }
+    *out = c;
+    return DSVE_OK;
+}
+
+dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *offsets,
+                            const double *A_g, const double *porosity, const double *dx,
+                            const int *bc_left, const int *bc_right, const double *q_in,
+                            const dsve_params *common, void *hip_stream)
+{
+    if (!out) return DSVE_E_ARG;
+    *out = nullptr;
+    std::string msg;
+    dsve_status st = check_common(common, msg);
+    if (st != DSVE_OK) return st;
+    if (n_channels < 1 || n_channels > (int64_t)1 << 30) return DSVE_E_ARG;
+    if (!offsets || !A_g || !porosity || !dx || !bc_left || !bc_right) return DSVE_E_ARG;
+    if (offsets[0] != 0) return DSVE_E_ARG;
+    for (int64_t k = 0; k < n_channels; ++k) {
+        if (offsets[k + 1] <= offsets[k]) return DSVE_E_ARG;
+        st = check_channel(A_g[k], porosity[k], dx[k], bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, msg);
+        if (st != DSVE_OK) return st;
+    }
+    dsve_ctx *c = new dsve_ctx();
+    c->batched = true;
+    c->precision = common->precision;
+    c->G = common->n_gauss;
+    c->g = common->g;
+    c->cfl = common->cfl;
+    c->n_channels = n_channels;
+    c->n_cells = offsets[n_channels];
+    c->h_off.assign(offsets, offsets + n_channels + 1);
+    c->h_ch.reserve(n_channels);
+    for (int64_t k = 0; k < n_channels; ++k)
+        c->h_ch.push_back(make_chan(offsets[k], offsets[k + 1] - offsets[k], A_g[k], porosity[k], dx[k],
+                                    bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, common->cfl));
+    st = setup(c, hip_stream);
+    if (st != DSVE_OK) {
+        release(c);
+        return st;
+    }
+    *out = c;
+    return DSVE_OK;
+}
+
+dsve_status dsve_destroy(dsve_ctx *ctx)
+{
+    if (!ctx) return DSVE_E_ARG;
+    release(ctx);
+    return DSVE_OK;
+}
+
+const char *dsve_last_error(const dsve_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+dsve_status dsve_clear_error(dsve_ctx *ctx)
+{
+    if (!ctx) return DSVE_E_ARG;
+    ctx->sticky = DSVE_OK;
+    ctx->err.clear();
+    HIP_TRY(ctx, launch_fill_u32(ctx->d_flags, 4, 0u, ctx->stream));
+    return DSVE_OK;
+}
+
+int dsve_device_cus(const dsve_ctx *ctx) { return ctx ? ctx->cus : 0; }
+
+dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, const double *zL,
+                           const double *hR, const double *qR, const double *zR, int64_t n,
+                           double *Dm, double *Dp)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (n < 0) return fail(ctx, DSVE_E_ARG, "n must be >= 0");
+    if (n == 0) return DSVE_OK;
+    if (!hL || !qL || !zL || !hR || !qR || !zR || !Dm || !Dp)
+        return fail(ctx, DSVE_E_ARG, "null pointer");
+    FluctArgs a{};
+    a.hL = hL; a.qL = qL; a.zL = zL; a.hR = hR; a.qR = qR; a.zR = zR;
+    a.Dm = Dm; a.Dp = Dp; a.flags = ctx->d_flags; a.n = n;
+    a.g = ctx->g; a.kq = ctx->h_ch[0].kq; a.rule = ctx->rule;
+    HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->stream));
+    return DSVE_OK;
+}
+
+dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const double *dt_dev,
+                        double *h, double *q, double *z)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (ctx->batched) return fail(ctx, DSVE_E_ARG, "cell_update needs a single-channel context");
+    if (!Dm || !Dp || !dt_dev || !h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
+    HIP_TRY(ctx, launch_cell_update(Dm, Dp, dt_dev, 0.0, ctx->h_ch[0].dx, ctx->n_cells, h, q, z,
+                                    ctx->stream));
+    return DSVE_OK;
+}
+
+static dsve_status enqueue_cfl(dsve_ctx *ctx, const double *h, const double *q, const double *z,
+                               unsigned long long *amax)
+{
+    HIP_TRY(ctx, launch_fill_u64(amax, ctx->n_channels, 0ull, ctx->stream));
+    CflArgs a{};
+    a.h = h; a.q = q; a.z = z; a.ch = ctx->d_ch; a.off = ctx->d_off; a.amax = amax;
+    a.flags = ctx->d_flags; a.n_cells = ctx->n_cells; a.n_channels = (int32_t)ctx->n_channels;
+    a.g = ctx->g;
+    HIP_TRY(ctx, launch_cfl(a, ctx->precision, ctx->stream));
+    return DSVE_OK;
+}
+
+dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const double *z,
+                       double *amax_dev, double *dt_dev)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (ctx->batched) return fail(ctx, DSVE_E_ARG, "cfl_reduce needs a single-channel context");
+    if (!h || !q || !z || !amax_dev || !dt_dev) return fail(ctx, DSVE_E_ARG, "null pointer");
+    if (((uintptr_t)amax_dev) & 7) return fail(ctx, DSVE_E_ARG, "amax_dev must be 8-byte aligned");
+    unsigned long long *am = reinterpret_cast<unsigned long long *>(amax_dev);
+    dsve_status st = enqueue_cfl(ctx, h, q, z, am);
+    if (st != DSVE_OK) return st;
+    HIP_TRY(ctx, launch_dt(am, ctx->d_ch, 1, dt_dev, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_amax, am, sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    ctx->last_amax_slot = 0;
+    return DSVE_OK;
+}
+
+// Arguments of step j (phase j mod 6) of a run starting from the caller's buffers.
+static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z, double *t)
+{
+    StepArgs a{};
+    const bool even = (j % 2) == 0;
+    a.h = even ? h : ctx->pp_h;
+    a.q = even ? q : ctx->pp_q;
+    a.z = even ? z : ctx->pp_z;
+    a.hn = even ? ctx->pp_h : h;
+    a.qn = even ? ctx->pp_q : q;
+    a.zn = even ? ctx->pp_z : z;
+    const int64_t C = ctx->n_channels;
+    a.ch = ctx->d_ch;
+    a.eoff = ctx->d_eoff;
+    a.tile_chan = ctx->d_tile_chan;
+    a.amax_cur = ctx->d_amax + (j % 3) * C;
+    a.amax_next = ctx->d_amax + ((j + 1) % 3) * C;
+    a.amax_clear = ctx->d_amax + ((j + 2) % 3) * C;
+    a.t = t;
+    a.flags = ctx->d_flags;
+    a.n_edges = ctx->n_edges;
+    a.n_tiles = ctx->n_tiles;
+    a.n_channels = (int32_t)C;
+    a.g = ctx->g;
+    a.rule = ctx->rule;
+    return a;
+}
+
+static int grid_of(const dsve_ctx *ctx)
+{
+    if (ctx->blocks_per_cu <= 0) return (int)std::min<int64_t>(ctx->n_tiles, INT32_MAX);
+    return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)ctx->blocks_per_cu * ctx->cus);
+}
+
+static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, double *t)
+{
+    const int grid = grid_of(ctx);
+    const void *key[4] = {h, q, z, t};
+    if (ctx->gexec && ctx->g_steps == ctx->graph_steps && ctx->g_tile == ctx->tile &&
+        ctx->g_grid == grid && std::equal(key, key + 4, ctx->g_key))
+        return DSVE_OK;
+    free_graph(ctx);
+    hipGraph_t graph = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < ctx->graph_steps; ++j) {
+        hipError_t e = launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->tile,
+                                   grid, ctx->cap_stream);
+        if (e != hipSuccess) {
+            (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(ctx, DSVE_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        }
+    }
+    HIP_TRY(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        ctx->gexec = nullptr;
+        return fail(ctx, DSVE_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    ctx->g_steps = ctx->graph_steps;
+    ctx->g_tile = ctx->tile;
+    ctx->g_grid = grid;
+    std::copy(key, key + 4, ctx->g_key);
+    return DSVE_OK;
+}
+
+static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps, double *t)
+{
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (!h || !q || !z || !t) return fail(ctx, DSVE_E_ARG, "null pointer");
+    if (n_steps < 0) return fail(ctx, DSVE_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return DSVE_OK;
+    const int64_t C = ctx->n_channels;
+    dsve_status st = build_tile_table(ctx, ctx->tile);
+    if (st != DSVE_OK) return st;
+    // slots: clear all three, CFL max of W^0 into slot 0
+    HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, 3 * C, 0ull, ctx->stream));
+    st = enqueue_cfl(ctx, h, q, z, ctx->d_amax);
+    if (st != DSVE_OK) return st;
+    int done = 0;
+    if (ctx->graph_steps > 0 && n_steps >= ctx->graph_steps) {
+        st = ensure_graph(ctx, h, q, z, t);
+        if (st != DSVE_OK) return st;
+        while (n_steps - done >= ctx->graph_steps) {
+            HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+            done += ctx->graph_steps;
+        }
+    }
+    const int grid = grid_of(ctx);
+    for (int j = done; j < n_steps; ++j)
+        HIP_TRY(ctx, launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->tile, grid,
+                                 ctx->stream));
+    if (n_steps % 2) {
+        const size_t bytes = sizeof(double) * ctx->n_cells;
+        HIP_TRY(ctx, hipMemcpyAsync(h, ctx->pp_h, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(q, ctx->pp_q, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(z, ctx->pp_z, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    ctx->last_amax_slot = n_steps % 3;
+    return DSVE_OK;
+}
+
+dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps, double *t_dev)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->batched) return fail(ctx, DSVE_E_ARG, "adot_step needs a single-channel context");
+    return run_steps(ctx, h, q, z, n_steps, t_dev);
+}
+
+dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                              double *t_dev)
+{
+    if (!ctx) return DSVE_E_ARG;
+    return run_steps(ctx, h, q, z, n_steps, t_dev);
+}
+
+dsve_status dsve_sync(dsve_ctx *ctx)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    else HIP_TRY(ctx, hipDeviceSynchronize());
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    unsigned int flags[4];
+    HIP_TRY(ctx, hipMemcpy(flags, ctx->d_flags, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags[0]) return fail(ctx, DSVE_E_NONHYPERBOLIC, "complex eigenvalues (arccos argument out of range)");
+    if (ctx->last_amax_slot >= 0) {
+        const int64_t C = ctx->n_channels;
+        std::vector<unsigned long long> am(C);
+        HIP_TRY(ctx, hipMemcpy(am.data(), ctx->d_amax + ctx->last_amax_slot * C, sizeof(unsigned long long) * C,
+                               hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < C; ++k) {
+            double v;
+            std::memcpy(&v, &am[k], sizeof v);
+            if (!std::isfinite(v) || !(v > 0.0)) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "non-finite or zero CFL speed in channel %lld", (long long)k);
+                return fail(ctx, DSVE_E_NONFINITE, buf);
+            }
+        }
+    }
+    return DSVE_OK;
+}
+
+dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int graph_steps)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (tile < 64 || tile > kMaxTile || (tile & (tile - 1)))
+        return fail(ctx, DSVE_E_ARG, "tile must be 64, 128 or 256");
+    if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(ctx, DSVE_E_ARG, "blocks_per_cu must be in [0, 32]");
+    if (graph_steps != 0 && (graph_steps % 6 || graph_steps < 6 || graph_steps > 600))
+        return fail(ctx, DSVE_E_ARG, "graph_steps must be 0 or a multiple of 6 in [6, 600]");
+    if (tile != ctx->tile) {
+        dsve_status st = build_tile_table(ctx, tile);
+        if (st != DSVE_OK) return st;
+    }
+    if (tile != ctx->tile || blocks_per_cu != ctx->blocks_per_cu || graph_steps != ctx->graph_steps)
+        free_graph(ctx);
+    ctx->tile = tile;
+    ctx->blocks_per_cu = blocks_per_cu;
+    ctx->graph_steps = graph_steps;
+    return DSVE_OK;
+}
+
+dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, int *graph_steps)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (tile) *tile = ctx->tile;
+    if (blocks_per_cu) *blocks_per_cu = ctx->blocks_per_cu;
+    if (graph_steps) *graph_steps = ctx->graph_steps;
+    return DSVE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner.
+static std::string tune_key(const dsve_ctx *ctx)
+{
+    // problem shape: channel count and a coarse histogram of channel lengths (log2 buckets)
+    int hist[40] = {0};
+    for (int64_t k = 0; k < ctx->n_channels; ++k) {
+        const int64_t n = ctx->h_off[k + 1] - ctx->h_off[k];
+        int b = 0;
+        while ((int64_t(1) << (b + 1)) <= n && b < 39) ++b;
+        ++hist[b];
+    }
+    std::ostringstream os;
+    os << ctx->arch << "|cu" << ctx->cus << "|p" << ctx->precision << "|G" << ctx->G << "|C"
+       << ctx->n_channels << "|N" << ctx->n_cells << "|h";
+    for (int b = 0; b < 40; ++b)
+        if (hist[b]) os << b << ":" << hist[b] << ",";
+    return os.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, int &tile, int &bpc)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    while (std::getline(f, line)) {
+        // one entry per line: {"key": "<key>", "tile": T, "blocks_per_cu": B}
+        const std::string pat = "\"key\": \"" + key + "\"";
+        if (line.find(pat) == std::string::npos) continue;
+        const size_t pt = line.find("\"tile\": ");
+        const size_t pb = line.find("\"blocks_per_cu\": ");
+        if (pt == std::string::npos || pb == std::string::npos) continue;
+        tile = std::atoi(line.c_str() + pt + 8);
+        bpc = std::atoi(line.c_str() + pb + 17);
+        return true;
+    }
+    return false;
+}
+
+static void cache_store(const char *path, const std::string &key, int tile, int bpc, double ms)
+{
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        const std::string pat = "\"key\": \"" + key + "\"";
+        while (f && std::getline(f, line))
+            if (!line.empty() && line.find(pat) == std::string::npos) keep.push_back(line);
+    }
+    std::ofstream o(path, std::ios::trunc);
+    for (auto &l : keep) o << l << "\n";
+    o << "{\"key\": \"" << key << "\", \"tile\": " << tile << ", \"blocks_per_cu\": " << bpc
+      << ", \"ms_per_step\": " << ms << "}\n";
+}
+
+extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q,
+                                     const double *z, int trial_steps, const char *cache_path)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (!h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
+    if (trial_steps < 2 || trial_steps > 1000) return fail(ctx, DSVE_E_ARG, "trial_steps must be in [2, 1000]");
+    const std::string key = tune_key(ctx);
+    int tile = 0, bpc = 0;
+    if (cache_lookup(cache_path, key, tile, bpc))
+        return dsve_set_launch(ctx, tile, bpc, ctx->graph_steps);
+
+    const size_t bytes = sizeof(double) * ctx->n_cells;
+    double *sh = nullptr, *sq = nullptr, *sz = nullptr, *st_ = nullptr;
+    HIP_TRY(ctx, hipMalloc(&sh, bytes));
+    HIP_TRY(ctx, hipMalloc(&sq, bytes));
+    HIP_TRY(ctx, hipMalloc(&sz, bytes));
+    HIP_TRY(ctx, hipMalloc(&st_, sizeof(double) * ctx->n_channels));
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    const int tiles[] = {64, 128, 256};
+    const int bpcs[] = {0, 2, 4, 8};
+    const int save_graph = ctx->graph_steps;
+    float best = 1e30f;
+    int best_tile = ctx->tile, best_bpc = ctx->blocks_per_cu;
+    dsve_status status = DSVE_OK;
+    for (int ti : tiles) {
+        for (int bi : bpcs) {
+            status = dsve_set_launch(ctx, ti, bi, 0);
+            if (status != DSVE_OK) break;
+            (void)hipMemcpyAsync(sh, h, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+            (void)hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+            (void)hipMemcpyAsync(sz, z, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+            (void)launch_fill_u64(reinterpret_cast<unsigned long long *>(st_), ctx->n_channels, 0ull, ctx->stream);
+            status = run_steps(ctx, sh, sq, sz, 2, st_);   // warm-up
+            if (status != DSVE_OK) break;
+            (void)hipEventRecord(e0, ctx->stream);
+            status = run_steps(ctx, sh, sq, sz, trial_steps, st_);
+            if (status != DSVE_OK) break;
+            (void)hipEventRecord(e1, ctx->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_tile = ti;
+                best_bpc = bi;
+            }
+        }
+        if (status != DSVE_OK) break;
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sh);
+    (void)hipFree(sq);
+    (void)hipFree(sz);
+    (void)hipFree(st_);
+    if (status != DSVE_OK) return status;
+    dsve_status st = dsve_set_launch(ctx, best_tile, best_bpc, save_graph);
+    if (st != DSVE_OK) return st;
+    cache_store(cache_path, key, best_tile, best_bpc, best / trial_steps);
+    return DSVE_OK;
+}

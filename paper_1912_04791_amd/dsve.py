@@ -1,0 +1,258 @@
+"""ctypes binding to libdsve.so (the C ABI of include/dsve.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory (float64 CUDA tensors) and the
+stream; nothing here computes any part of the scheme.  If the library is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsve.so")
+
+OK = 0
+E_ARG = -1
+E_HIP = -2
+E_NONFINITE = -3
+E_NONHYPERBOLIC = -4
+E_UNSUPPORTED = -5
+
+BC_TRANSMISSIVE = 0
+BC_PERIODIC = 1
+BC_INFLOW_Q = 2
+LAW_GRASS = 0
+FP64 = 0
+MIXED = 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1912_04791_amd.build` "
+        "(there is no fallback path)")
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``dsve_params``."""
+    _fields_ = [
+        ("g", ctypes.c_double),
+        ("porosity", ctypes.c_double),
+        ("law", ctypes.c_int),
+        ("A_g", ctypes.c_double),
+        ("law_extra", ctypes.c_double * 4),
+        ("n_gauss", ctypes.c_int),
+        ("cfl", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("bc_left", ctypes.c_int),
+        ("bc_right", ctypes.c_int),
+        ("q_in", ctypes.c_double),
+        ("precision", ctypes.c_int),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_ctxp = ctypes.c_void_p
+
+lib = ctypes.CDLL(LIB_PATH)
+lib.dsve_abi_version.restype = ctypes.c_int
+lib.dsve_init.argtypes = [ctypes.POINTER(_ctxp), ctypes.POINTER(Params), _i64, _vp]
+lib.dsve_batch_init.argtypes = [ctypes.POINTER(_ctxp), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                ctypes.POINTER(Params), _vp]
+lib.dsve_destroy.argtypes = [_ctxp]
+lib.dot_edge_fluct.argtypes = [_ctxp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]
+lib.cell_update.argtypes = [_ctxp, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.cfl_reduce.argtypes = [_ctxp, _vp, _vp, _vp, _vp, _vp]
+lib.adot_step.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, _vp]
+lib.adot_step_batched.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, _vp]
+lib.dsve_sync.argtypes = [_ctxp]
+lib.dsve_last_error.argtypes = [_ctxp]
+lib.dsve_last_error.restype = ctypes.c_char_p
+lib.dsve_clear_error.argtypes = [_ctxp]
+lib.dsve_set_launch.argtypes = [_ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+lib.dsve_get_launch.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]
+lib.dsve_autotune.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_char_p]
+lib.dsve_device_cus.argtypes = [_ctxp]
+lib.dsve_device_cus.restype = ctypes.c_int
+assert lib.dsve_abi_version() == 1, "libdsve ABI version mismatch"
+
+ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destroy",
+                "dot_edge_fluct", "cell_update", "cfl_reduce", "adot_step", "adot_step_batched",
+                "dsve_sync", "dsve_last_error", "dsve_clear_error", "dsve_set_launch",
+                "dsve_get_launch", "dsve_autotune", "dsve_device_cus")
+
+
+class DsveError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dsve status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
+                bc_left=BC_TRANSMISSIVE, bc_right=BC_TRANSMISSIVE, q_in=0.0,
+                precision="fp64") -> Params:
+    p = Params()
+    p.g = g
+    p.porosity = porosity
+    p.law = LAW_GRASS
+    p.A_g = A_g
+    for k in range(4):
+        p.law_extra[k] = 0.0
+    p.n_gauss = n_gauss
+    p.cfl = cfl
+    p.dx = dx
+    p.bc_left = bc_left
+    p.bc_right = bc_right
+    p.q_in = q_in
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return p
+
+
+class Context:
+    """One libdsve context (single channel or batched).  Methods map 1:1 to entry points."""
+
+    def __init__(self, handle, n_cells: int, n_channels: int, batched: bool):
+        self._h = handle
+        self.n_cells = n_cells
+        self.n_channels = n_channels
+        self.batched = batched
+
+    # -- construction -----------------------------------------------------
+    @classmethod
+    def single(cls, n_cells: int, stream=None, **params) -> "Context":
+        p = make_params(**params)
+        h = _ctxp()
+        st = lib.dsve_init(ctypes.byref(h), ctypes.byref(p), int(n_cells), _stream_handle(stream))
+        if st != OK:
+            raise DsveError(st, "dsve_init failed")
+        return cls(h, int(n_cells), 1, False)
+
+    @classmethod
+    def batch(cls, offsets, A_g, porosity, dx, bc_left, bc_right, q_in=None, stream=None,
+              **common) -> "Context":
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        C = off.size - 1
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (A_g, porosity, dx)]
+        bcl = np.ascontiguousarray(bc_left, dtype=np.int32)
+        bcr = np.ascontiguousarray(bc_right, dtype=np.int32)
+        qin = np.ascontiguousarray(np.zeros(C) if q_in is None else q_in, dtype=np.float64)
+        for a in (*arrs, bcl, bcr, qin):
+            assert a.size == C
+        p = make_params(**common)
+        h = _ctxp()
+        st = lib.dsve_batch_init(ctypes.byref(h), C, off.ctypes.data, arrs[0].ctypes.data,
+                                 arrs[1].ctypes.data, arrs[2].ctypes.data, bcl.ctypes.data,
+                                 bcr.ctypes.data, qin.ctypes.data, ctypes.byref(p),
+                                 _stream_handle(stream))
+        if st != OK:
+            raise DsveError(st, "dsve_batch_init failed")
+        return cls(h, int(off[-1]), C, True)
+
+    @classmethod
+    def from_workload(cls, wl, precision=None, stream=None) -> "Context":
+        """Context for an ``inputs.Workload`` (single channel when it has one channel)."""
+        prec = precision or wl.precision
+        if wl.n_channels == 1:
+            return cls.single(wl.n_cells, stream=stream, g=wl.g, porosity=float(wl.porosity[0]),
+                              A_g=float(wl.Ag[0]), n_gauss=wl.n_gauss, cfl=wl.cfl,
+                              dx=float(wl.dx[0]), bc_left=int(wl.bc_left[0]),
+                              bc_right=int(wl.bc_right[0]), q_in=float(wl.q_in[0]),
+                              precision=prec)
+        return cls.batch(wl.offsets, wl.Ag, wl.porosity, wl.dx, wl.bc_left, wl.bc_right, wl.q_in,
+                         stream=stream, g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl, precision=prec)
+
+    # -- helpers ----------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != OK:
+            msg = lib.dsve_last_error(self._h)
+            raise DsveError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if self._h:
+            lib.dsve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points -----------------------------------------------------
+    def dot_edge_fluct(self, hL, qL, zL, hR, qR, zR, Dm, Dp):
+        n = hL.numel()
+        self._check(lib.dot_edge_fluct(self._h, _ptr(hL), _ptr(qL), _ptr(zL), _ptr(hR), _ptr(qR),
+                                       _ptr(zR), n, _ptr(Dm), _ptr(Dp)), "dot_edge_fluct")
+
+    def cell_update(self, Dm, Dp, dt, h, q, z):
+        self._check(lib.cell_update(self._h, _ptr(Dm), _ptr(Dp), _ptr(dt), _ptr(h), _ptr(q),
+                                    _ptr(z)), "cell_update")
+
+    def cfl_reduce(self, h, q, z, amax, dt):
+        self._check(lib.cfl_reduce(self._h, _ptr(h), _ptr(q), _ptr(z), _ptr(amax), _ptr(dt)),
+                    "cfl_reduce")
+
+    def adot_step(self, h, q, z, n_steps: int, t):
+        fn = lib.adot_step_batched if self.batched else lib.adot_step
+        self._check(fn(self._h, _ptr(h), _ptr(q), _ptr(z), int(n_steps), _ptr(t)), "adot_step")
+
+    def sync(self):
+        self._check(lib.dsve_sync(self._h), "dsve_sync")
+
+    def sync_status(self) -> int:
+        return lib.dsve_sync(self._h)
+
+    def last_error(self) -> str:
+        m = lib.dsve_last_error(self._h)
+        return m.decode() if m else ""
+
+    def clear_error(self):
+        self._check(lib.dsve_clear_error(self._h), "dsve_clear_error")
+
+    def set_launch(self, tile: int = 256, blocks_per_cu: int = 0, graph_steps: int = 60):
+        self._check(lib.dsve_set_launch(self._h, tile, blocks_per_cu, graph_steps), "dsve_set_launch")
+
+    def get_launch(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(lib.dsve_get_launch(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                    "dsve_get_launch")
+        return a.value, b.value, c.value
+
+    def autotune(self, h, q, z, trial_steps: int = 10, cache_path: str | None = None):
+        cp = cache_path.encode() if cache_path else None
+        self._check(lib.dsve_autotune(self._h, _ptr(h), _ptr(q), _ptr(z), trial_steps, cp),
+                    "dsve_autotune")
+
+    def device_cus(self) -> int:
+        return lib.dsve_device_cus(self._h)
+
+
+def upload(wl, device="cuda"):
+    """Device float64 copies of a workload's state and a zeroed clock per channel."""
+    import torch
+    h = torch.from_numpy(np.ascontiguousarray(wl.h)).to(device)
+    q = torch.from_numpy(np.ascontiguousarray(wl.q)).to(device)
+    z = torch.from_numpy(np.ascontiguousarray(wl.z)).to(device)
+    t = torch.zeros(wl.n_channels, dtype=torch.float64, device=device)
+    return h, q, z, t

@@ -170,22 +170,29 @@ def make_c2(n_cells: int = 1 << 20, steps: int = 1000, seed: int = 2, length: fl
 
 
 def bernoulli_depth(z: np.ndarray, q: float, H: float, g: float, supercritical: np.ndarray,
-                    iters: int = 60) -> np.ndarray:
+                    iters: int = 80) -> np.ndarray:
     """Depth h solving h + q^2/(2 g h^2) + z = H, on the chosen branch (Newton, FP64).
 
     Physics of the initial condition only (frictionless steady energy balance).
+    Cells whose iterate has stopped moving leave the active set.
     """
     hc = (q * q / g) ** (1.0 / 3.0)
     E = H - z
     h = np.where(supercritical, 0.5 * hc, np.maximum(E, 1.5 * hc))
+    idx = np.arange(h.size)
     for _ in range(iters):
-        f = h + q * q / (2.0 * g * h * h) - E
-        df = 1.0 - q * q / (g * h ** 3)
+        if idx.size == 0:
+            break
+        hh, EE, sup = h[idx], E[idx], supercritical[idx]
+        f = hh + q * q / (2.0 * g * hh * hh) - EE
+        df = 1.0 - q * q / (g * hh ** 3)
         step = f / np.where(np.abs(df) > 1e-14, df, 1e-14)
-        h_new = h - step
+        h_new = hh - step
         # stay on the branch: subcritical h >= hc, supercritical h <= hc
-        h_new = np.where(supercritical, np.clip(h_new, 1e-6, hc), np.maximum(h_new, hc))
-        h = h_new
+        h_new = np.where(sup, np.clip(h_new, 1e-6, hc), np.maximum(h_new, hc))
+        moving = np.abs(h_new - hh) > 1e-15 * hc
+        h[idx] = h_new
+        idx = idx[moving]
     return h
 
 

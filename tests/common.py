@@ -1,0 +1,42 @@
+"""Shared helpers for the tests (no method arithmetic here)."""
+import numpy as np
+
+import oracle
+from paper_1912_04791_amd import inputs
+
+
+def spec_of(wl: inputs.Workload, c: int = 0) -> "oracle.ChannelSpec":
+    return oracle.ChannelSpec(n_cells=int(wl.lengths()[c]), dx=float(wl.dx[c]), Ag=float(wl.Ag[c]),
+                              porosity=float(wl.porosity[c]), g=wl.g, n_gauss=wl.n_gauss,
+                              cfl=wl.cfl, bc_left=int(wl.bc_left[c]), bc_right=int(wl.bc_right[c]),
+                              q_in=float(wl.q_in[c]))
+
+
+def oracle_run(wl: inputs.Workload, steps: int | None = None, nthreads: int | None = None):
+    """Oracle result of a workload: (h, q, z, t[C])."""
+    n = wl.steps if steps is None else steps
+    if wl.n_channels == 1:
+        h, q, z, t = oracle.run(spec_of(wl), wl.h, wl.q, wl.z, n, nthreads=nthreads)
+        return h, q, z, np.array([t])
+    specs = [spec_of(wl, c) for c in range(wl.n_channels)]
+    return oracle.run_batched(specs, wl.offsets, wl.h, wl.q, wl.z, n, nthreads=nthreads)
+
+
+def rel_l1(a: np.ndarray, ref: np.ndarray, h_ref: np.ndarray) -> float:
+    """||a - ref||_1 / max(||ref||_1, 1e-3 ||h_ref||_1) (per variable)."""
+    den = max(np.abs(ref).sum(), 1e-3 * np.abs(h_ref).sum())
+    return float(np.abs(a - ref).sum() / den)
+
+
+def max_rel_l1(got, ref) -> float:
+    """Largest relative L1 error over h, q, z."""
+    return max(rel_l1(g, r, ref[0]) for g, r in zip(got[:3], ref[:3]))
+
+
+def per_channel_rel_l1(got, ref, offsets) -> np.ndarray:
+    C = len(offsets) - 1
+    out = np.zeros(C)
+    for c in range(C):
+        lo, hi = offsets[c], offsets[c + 1]
+        out[c] = max(rel_l1(g[lo:hi], r[lo:hi], ref[0][lo:hi]) for g, r in zip(got[:3], ref[:3]))
+    return out

@@ -1,0 +1,255 @@
+"""FP64 HIP path vs the CPU oracle, through the C ABI (MI355X).
+
+Bar: relative L1 <= 1e-12 per variable for whole runs (the FP64 tolerance);
+pairwise fluctuations and the CFL maximum are held to the same bar per edge set.
+Sizes span several tiles and ragged tails; full-size cases (2^20 and 2^24 cells)
+run a few steps of the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04791_amd import inputs
+
+from common import max_rel_l1, oracle_run, per_channel_rel_l1, spec_of
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dsve():
+    from paper_1912_04791_amd import dsve as d
+    return d
+
+
+def run_gpu(dsve, torch, wl, steps=None, precision="fp64", launch=None):
+    ctx = dsve.Context.from_workload(wl, precision=precision)
+    if launch is not None:
+        ctx.set_launch(*launch)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, wl.steps if steps is None else steps, t)
+    ctx.sync()
+    out = (h.cpu().numpy(), q.cpu().numpy(), z.cpu().numpy(), t.cpu().numpy())
+    ctx.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("G", [1, 2, 3, 4, 5])
+def test_pairwise_fluct_matches_oracle(torch_dev, dsve, G):
+    torch = torch_dev
+    n = 100_003
+    WL, WR = inputs.make_random_edges(n, seed=100 + G)
+    xi_p, Ag = 0.4, 0.02
+    ctx = dsve.Context.single(16, porosity=xi_p, A_g=Ag, n_gauss=G, dx=1.0)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (*WL, *WR)]
+    Dm = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    Dp = torch.zeros_like(Dm)
+    ctx.dot_edge_fluct(*dev, Dm, Dp)
+    ctx.sync()
+    rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / (1.0 - xi_p), Ag, G=G)
+    gm, gp = Dm.cpu().numpy(), Dp.cpu().numpy()
+    for got, ref in ((gm, rm), (gp, rp)):
+        l1 = np.abs(got - ref).sum() / np.abs(ref).sum()
+        assert l1 <= TOL, l1
+        # per edge, relative to the edge's own fluctuation size
+        sc = np.abs(rm).max(axis=0) + np.abs(rp).max(axis=0)
+        per = np.abs(got - ref).max(axis=0) / sc
+        assert np.quantile(per, 0.999) <= 1e-12 and per.max() <= 1e-8, (per.max(), np.argmax(per))
+    ctx.close()
+
+
+def test_cfl_reduce_matches_oracle(torch_dev, dsve):
+    torch = torch_dev
+    wl = inputs.make_c3(n_cells=300_001)
+    ctx = dsve.Context.from_workload(wl, precision="fp64")
+    h, q, z, _ = dsve.upload(wl)
+    amax = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.cfl_reduce(h, q, z, amax, dt)
+    ctx.sync()
+    ref = oracle.cfl_amax(wl.h, wl.q, wl.z, 9.81, 1.0 / (1 - wl.porosity[0]), wl.Ag[0])
+    assert abs(float(amax[0]) - ref) <= 1e-14 * ref
+    assert abs(float(dt[0]) - wl.cfl * wl.dx[0] / ref) <= 1e-14 * float(dt[0])
+    ctx.close()
+
+
+def test_cell_update_matches_oracle_step(torch_dev, dsve):
+    torch = torch_dev
+    wl = inputs.make_c2(n_cells=5000)
+    xi = 1.0 / (1.0 - wl.porosity[0])
+    N = wl.n_cells
+    # edge states with periodic ghosts; fluctuations from the oracle
+    hL, qL, zL = (np.concatenate([a[-1:], a]) for a in (wl.h, wl.q, wl.z))
+    hR, qR, zR = (np.concatenate([a, a[:1]]) for a in (wl.h, wl.q, wl.z))
+    Dm, Dp = oracle.fluct((hL, qL, zL), (hR, qR, zR), 9.81, xi, wl.Ag[0])
+    dt = 1.3e-4
+    ref = oracle.step(wl.h, wl.q, wl.z, [wl.h[-1], wl.q[-1], wl.z[-1]], [wl.h[0], wl.q[0], wl.z[0]],
+                      9.81, xi, wl.Ag[0], 3, dt, wl.dx[0])
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, _ = dsve.upload(wl)
+    tDm = torch.from_numpy(np.ascontiguousarray(Dm)).cuda()
+    tDp = torch.from_numpy(np.ascontiguousarray(Dp)).cuda()
+    tdt = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ctx.cell_update(tDm, tDp, tdt, h, q, z)
+    ctx.sync()
+    assert N + 1 == Dm.shape[1]
+    # one update is W - r s; allow a few roundings of the operands (FMA contraction on the GPU)
+    eps = np.finfo(np.float64).eps
+    for got, r, w0 in zip((h, q, z), ref, (wl.h, wl.q, wl.z)):
+        g = got.cpu().numpy()
+        assert np.all(np.abs(g - r) <= 4 * eps * (np.abs(w0) + np.abs(w0 - r)))
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+def test_c1_full_run(torch_dev, dsve):
+    wl = inputs.make_c1()
+    got = run_gpu(dsve, torch_dev, wl)
+    ref = oracle_run(wl)
+    assert max_rel_l1(got, ref) <= TOL
+    assert abs(got[3][0] - ref[3][0]) <= 1e-12 * ref[3][0]
+
+
+@pytest.mark.parametrize("n_cells,steps", [(1, 7), (2, 6), (254, 13), (255, 12), (256, 61),
+                                           (257, 121), (16_385, 100)])
+def test_ragged_sizes_and_odd_steps(torch_dev, dsve, n_cells, steps):
+    wl = inputs.make_c2(n_cells=max(n_cells, 1), steps=steps, length=1000.0 * n_cells / (1 << 20) + 1e-3,
+                        max_mode=min(64, max(1, n_cells // 4)))
+    got = run_gpu(dsve, torch_dev, wl)
+    ref = oracle_run(wl)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("bc", ["transmissive", "inflow"])
+def test_c3_shape_reduced(torch_dev, dsve, bc):
+    wl = inputs.make_c3(n_cells=1 << 14, steps=150)
+    if bc == "transmissive":
+        wl.bc_left[:] = inputs.BC_TRANSMISSIVE
+    got = run_gpu(dsve, torch_dev, wl, precision="fp64")
+    ref = oracle_run(wl)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+def test_c4_shape_batched_reduced(torch_dev, dsve):
+    wl = inputs.make_c4(n_channels=48, len_lo=64, len_hi=3000, steps=60)
+    got = run_gpu(dsve, torch_dev, wl)
+    ref = oracle_run(wl)
+    per = per_channel_rel_l1(got, ref, wl.offsets)
+    assert per.max() <= TOL, (per.max(), per.argmax())
+    np.testing.assert_allclose(got[3], ref[3], rtol=1e-12)
+
+
+def test_c5_shape_batched_reduced_fp64(torch_dev, dsve):
+    wl = inputs.make_c5(n_channels=64, len_lo=100, len_hi=700, steps=80)
+    got = run_gpu(dsve, torch_dev, wl, precision="fp64")
+    ref = oracle_run(wl)
+    per = per_channel_rel_l1(got, ref, wl.offsets)
+    assert per.max() <= TOL, (per.max(), per.argmax())
+
+
+def test_single_cell_channels_batched(torch_dev, dsve):
+    # channels as short as one cell, mixed with long ones
+    base = inputs.make_c4(n_channels=10, len_lo=1, len_hi=600, steps=9)
+    got = run_gpu(dsve, torch_dev, base)
+    ref = oracle_run(base)
+    per = per_channel_rel_l1(got, ref, base.offsets)
+    assert per.max() <= TOL
+
+
+# ---------------------------------------------------------------------------
+def test_launch_configuration_does_not_change_bits(torch_dev, dsve):
+    wl = inputs.make_c4(n_channels=12, len_lo=100, len_hi=5000, steps=37)
+    outs = []
+    for launch in [(256, 0, 60), (64, 0, 0), (128, 2, 6), (256, 4, 12), (64, 8, 36)]:
+        outs.append(run_gpu(dsve, torch_dev, wl, launch=launch))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_repeat_runs_are_bitwise_identical(torch_dev, dsve):
+    wl = inputs.make_c2(n_cells=70_000, steps=66)
+    a = run_gpu(dsve, torch_dev, wl)
+    b = run_gpu(dsve, torch_dev, wl)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_split_run_equals_straight_run(torch_dev, dsve):
+    # checkpoint/resume: k steps, copy state to host and back, k more == 2k straight
+    torch = torch_dev
+    wl = inputs.make_c1(steps=0)
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, 70, t)
+    ctx.sync()
+    saved = [x.cpu() for x in (h, q, z, t)]
+    h2, q2, z2, t2 = (x.cuda() for x in saved)
+    ctx.adot_step(h2, q2, z2, 70, t2)
+    ctx.sync()
+    h1, q1, z1, t1 = dsve.upload(wl)
+    ctx.adot_step(h1, q1, z1, 140, t1)
+    ctx.sync()
+    for a, b in ((h1, h2), (q1, q2), (z1, z2)):
+        assert torch.equal(a, b)
+    assert abs(float(t1[0]) - float(t2[0])) <= 1e-14 * float(t1[0])
+    ctx.close()
+
+
+def test_zero_steps_is_a_no_op(torch_dev, dsve):
+    wl = inputs.make_c1()
+    got = run_gpu(dsve, torch_dev, wl, steps=0)
+    assert np.array_equal(got[0], wl.h) and np.array_equal(got[2], wl.z) and got[3][0] == 0.0
+
+
+# ---------------------------------------------------------------------------
+def test_full_size_c2_few_steps(torch_dev, dsve):
+    wl = inputs.make_c2()
+    got = run_gpu(dsve, torch_dev, wl, steps=3)
+    ref = oracle_run(wl, steps=3)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+def test_full_size_c3_two_steps_fp64(torch_dev, dsve):
+    wl = inputs.make_c3()
+    got = run_gpu(dsve, torch_dev, wl, steps=2, precision="fp64")
+    ref = oracle_run(wl, steps=2)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+# ---------------------------------------------------------------------------
+def test_nonfinite_state_is_reported(torch_dev, dsve):
+    wl = inputs.make_c1(n_cells=300, steps=5)
+    wl.h[17] = -0.5
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, 5, t)
+    assert ctx.sync_status() == dsve.E_NONFINITE
+    # sticky until cleared
+    assert ctx.sync_status() == dsve.E_NONFINITE
+    ctx.clear_error()
+    h, q, z, t = dsve.upload(inputs.make_c1(n_cells=300, steps=5))
+    ctx.adot_step(h, q, z, 5, t)
+    ctx.sync()
+    ctx.close()
+
+
+def test_bad_launch_arguments(torch_dev, dsve):
+    wl = inputs.make_c1()
+    ctx = dsve.Context.from_workload(wl)
+    for bad in [(96, 0, 60), (512, 0, 60), (256, -1, 60), (256, 0, 7)]:
+        with pytest.raises(dsve.DsveError):
+            ctx.set_launch(*bad)
+        ctx.clear_error()
+    ctx.close()
