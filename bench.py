@@ -1,0 +1,259 @@
+"""Benchmark of the A-DOT hot path on one MI355X: edge updates per second.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+A "step" is one time step of the whole hot path over the workload: ghost cells,
+CFL time step, DOT fluctuation at every edge, cell update, next CFL maximum
+(one fused kernel).  W untimed warm-up steps, then exactly K timed steps with
+the state already resident in HBM; the timed region is bracketed by device
+synchronisation and measured with HIP events on the stream the kernels run on.
+
+Prints ONE JSON line (rank 0) with the FP64 figure as ``value``, the mixed form
+beside it, the roofline of the fused step kernel, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "A-DOT edge updates/s, FP64 vs FP32-mixed at stated L1 err; % VALU peak"
+UNIT = "edge-updates/s"
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA)
+FP32_VALU_PEAK_TFLOPS = 78.6   # same rate without packed FP32 (packed FP32 is disabled)
+
+# Algorithmic operation count of one edge update at G = 3 in the form the kernel evaluates
+# (each +, -, *, / and each sqrt, acos, sin, cos counted as one; an FMA as two):
+# per quadrature node 141 (eigenvalues 46, A dW and |A| dW 91, path node 4), per edge
+# 3 x 141 + 15, per cell update 11 plus its CFL speed 48.  Derivation in the design doc.
+OPS_PER_NODE = 141
+OPS_PER_EDGE_EXTRA = 15
+OPS_PER_CELL = 59
+
+
+def ops_per_edge_update(G: int = 3) -> int:
+    return G * OPS_PER_NODE + OPS_PER_EDGE_EXTRA + OPS_PER_CELL
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1912_04791_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(ROOT, "paper_1912_04791_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per step-kernel launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = d.get(f"{workload}:{precision}")
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def make_workload(name: str):
+    from paper_1912_04791_amd import inputs
+    return inputs.MAKERS[name]()
+
+
+def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None):
+    import torch
+    from paper_1912_04791_amd import dsve
+
+    stream = torch.cuda.current_stream()
+    ctx = dsve.Context.from_workload(wl, precision=precision, stream=stream)
+    if launch:
+        ctx.set_launch(*launch)
+    h, q, z, t = dsve.upload(wl)
+    if launch is None:
+        # pick tile and persistent grid size on a scratch copy (outside the timed region)
+        ctx.autotune(h, q, z, trial_steps=20)
+    if warmup > 0:
+        ctx.adot_step(h, q, z, warmup, t)
+    ctx.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    ctx.adot_step(h, q, z, steps, t)
+    e1.record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    res = {"ms_total": ms, "wall_s": wall, "launch": ctx.get_launch(), "cus": ctx.device_cus()}
+    ctx.close()
+    return res
+
+
+def gpu_state_after(wl, precision: str, steps: int):
+    import torch
+    from paper_1912_04791_amd import dsve
+    ctx = dsve.Context.from_workload(wl, precision=precision)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, steps, t)
+    ctx.sync()
+    torch.cuda.synchronize()
+    out = (h.cpu().numpy(), q.cpu().numpy(), z.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def rel_l1_max(got, ref) -> float:
+    hs = np.abs(ref[0]).sum()
+    return float(max(np.abs(g - r).sum() / max(np.abs(r).sum(), 1e-3 * hs)
+                     for g, r in zip(got, ref)))
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    """The oracle as it stands, on this host's cores, on a bounded number of steps of the
+    same workload.  Returns the baseline dict and the oracle state (for the L1 errors)."""
+    import oracle
+    spec = oracle.ChannelSpec(n_cells=wl.n_cells, dx=float(wl.dx[0]), Ag=float(wl.Ag[0]),
+                              porosity=float(wl.porosity[0]), g=wl.g, n_gauss=wl.n_gauss,
+                              cfl=wl.cfl, bc_left=int(wl.bc_left[0]), bc_right=int(wl.bc_right[0]),
+                              q_in=float(wl.q_in[0]))
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    oracle.run(spec, wl.h, wl.q, wl.z, 1, nthreads=threads)
+    one = time.perf_counter() - t0
+    n = int(max(1, min(wl.steps, budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    h, q, z, _ = oracle.run(spec, wl.h, wl.q, wl.z, n, nthreads=threads)
+    el = time.perf_counter() - t0
+    eu = wl.edges_per_step() * n
+    base = {"value": eu / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{wl.name}: first {n} of {wl.steps} steps at full size "
+                      f"({wl.n_cells} cells), {el:.1f} s on {threads} threads"}
+    return base, (h, q, z), n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--precisions", default="fp64,mixed")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=-1)
+    ap.add_argument("--graph-steps", type=int, default=-1)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "kernel for scaling HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
+
+    wl = make_workload(args.workload)
+    edges = wl.edges_per_step()
+    launch = None
+    if args.tile or args.blocks_per_cu >= 0 or args.graph_steps >= 0:
+        launch = (args.tile or 256, max(args.blocks_per_cu, 0),
+                  60 if args.graph_steps < 0 else args.graph_steps)
+
+    precisions = [p for p in args.precisions.split(",") if p]
+    results = {}
+    for prec in precisions:
+        r = time_gpu(wl, prec, args.steps, args.warmup, launch)
+        r["edge_updates_per_s"] = edges * args.steps / (r["ms_total"] * 1e-3)
+        r["ms_per_step"] = r["ms_total"] / args.steps
+        print(f"[bench] {wl.name} {prec}: {r['ms_per_step'] * 1e3:.2f} us/step, "
+              f"{r['edge_updates_per_s']:.4e} edge-updates/s", file=sys.stderr, flush=True)
+        results[prec] = r
+
+    main_prec = precisions[0]
+    main = results[main_prec]
+    ops = ops_per_edge_update(wl.n_gauss)
+    achieved_tflops = edges * ops / (main["ms_per_step"] * 1e-3) / 1e12
+    peak = FP64_VALU_PEAK_TFLOPS if main_prec == "fp64" else FP32_VALU_PEAK_TFLOPS
+    traffic = measured_traffic(wl.name, main_prec)
+
+    out = {
+        "metric": METRIC,
+        "value": main["edge_updates_per_s"],
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: periodic single channel, N=2^20 cells, L=1000 m, "
+                               f"A_g=0.005, porosity 0.4, G=3, CFL 0.9" if wl.name == "c2"
+                   else wl.name,
+                   "n_cells": wl.n_cells, "n_channels": wl.n_channels,
+                   "edges_per_step": edges, "precision": main_prec,
+                   "launch": {"tile": main["launch"][0], "blocks_per_cu": main["launch"][1],
+                              "graph_steps": main["launch"][2]},
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / peak,
+                     "traffic": traffic, "kernel": "k_step<3, FP64>" if main_prec == "fp64"
+                     else "k_step<3, MIXED>", "ops_per_edge_update": ops},
+    }
+    for prec in precisions[1:]:
+        r = results[prec]
+        out[prec] = {"value": r["edge_updates_per_s"], "ms_per_step": r["ms_per_step"],
+                     "speedup_vs_" + main_prec: r["edge_updates_per_s"] / main["edge_updates_per_s"]}
+
+    if not args.no_cpu:
+        base, ref, n = cpu_baseline(wl)
+        out["cpu_baseline"] = base
+        errs = {}
+        for prec in precisions:
+            errs[prec] = rel_l1_max(gpu_state_after(wl, prec, n), ref)
+        out["l1_vs_oracle"] = {"steps": n, **errs}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

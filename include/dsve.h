@@ -165,8 +165,8 @@ dsve_status dsve_clear_error(dsve_ctx *ctx);
 
 /* Launch configuration of the fused step kernel.
  *   tile           threads (= edges) per workgroup: 64, 128 or 256
- *   blocks_per_cu  persistent workgroups per compute unit (1..32); 0 = one
- *                  workgroup per tile (no persistence)
+ *   blocks_per_cu  persistent workgroups per compute unit (1..32); 0 = as many
+ *                  as fit on a compute unit at once (occupancy of the kernel)
  *   graph_steps    steps per captured HIP graph: a multiple of 6 in [6, 600],
  *                  or 0 to launch every step directly
  * The results do not depend on these (each edge and cell is computed the same

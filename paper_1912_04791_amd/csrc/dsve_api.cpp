@@ -424,10 +424,13 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
     return a;
 }
 
+// Persistent grid: blocks_per_cu workgroups per compute unit (0 = as many as fit at once),
+// never more than there are tiles.
 static int grid_of(const dsve_ctx *ctx)
 {
-    if (ctx->blocks_per_cu <= 0) return (int)std::min<int64_t>(ctx->n_tiles, INT32_MAX);
-    return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)ctx->blocks_per_cu * ctx->cus);
+    const int bpc = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
+                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->tile);
+    return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)bpc * ctx->cus);
 }
 
 static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, double *t)
@@ -650,7 +653,7 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     const int tiles[] = {64, 128, 256};
-    const int bpcs[] = {0, 2, 4, 8};
+    const int bpcs[] = {0, 1, 2, 3, 4, 6, 8};
     const int save_graph = ctx->graph_steps;
     float best = 1e30f;
     int best_tile = ctx->tile, best_bpc = ctx->blocks_per_cu;

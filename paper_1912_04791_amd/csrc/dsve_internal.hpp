@@ -83,6 +83,8 @@ struct FluctArgs {
 // hipError_t of the launch.
 hipError_t launch_step(const StepArgs &a, int precision, int G, int tile, int grid,
                        hipStream_t stream);
+// Workgroups of the step kernel that fit on one compute unit at once (occupancy query).
+int step_blocks_per_cu(int precision, int G, int tile);
 hipError_t launch_cfl(const CflArgs &a, int precision, hipStream_t stream);
 hipError_t launch_fluct(const FluctArgs &a, int precision, int G, hipStream_t stream);
 hipError_t launch_cell_update(const double *Dm, const double *Dp, const double *dt,

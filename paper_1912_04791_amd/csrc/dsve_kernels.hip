@@ -65,13 +65,15 @@ __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, doub
                                            double zR, double g, double kq, const GaussRule &rule,
                                            double Dm[3], double Dp[3], bool &bad)
 {
-    fluct64<G>(hL, qL, zL, hR, qR, zR, g, kq, rule, Dm, Dp, bad);
+    if constexpr (PREC == PREC_FP64) fluct64<G>(hL, qL, zL, hR, qR, zR, g, kq, rule, Dm, Dp, bad);
+    else fluct_mixed<G>(hL, qL, zL, hR, qR, zR, g, kq, rule, Dm, Dp, bad);
 }
 
 template <int PREC>
 __device__ __forceinline__ double cell_speed(double h, double q, double g, double kq, bool &bad)
 {
-    return speed64(h, q, g, kq, bad);
+    if constexpr (PREC == PREC_FP64) return speed64(h, q, g, kq, bad);
+    else return speed_mixed(h, q, g, kq, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -166,28 +168,44 @@ __device__ __forceinline__ int find_channel(const int64_t *off, int C, int64_t i
     return lo;
 }
 
+// Grid-stride over cells; each workgroup keeps its running maximum for one channel at a
+// time and flushes it with one global atomic when the channel changes (cells are visited in
+// increasing order within a workgroup, so channels change monotonically).
 template <int PREC>
 __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
 {
     __shared__ unsigned long long s_acc;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < A.n_cells;
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
-    const int home = find_channel(A.off, A.n_channels, i0 < A.n_cells ? i0 : A.n_cells - 1);
-    if (threadIdx.x == 0) s_acc = 0ull;
-    __syncthreads();
-    int c = home;
-    unsigned long long bits = 0ull;
-    bool bad = false;
-    if (active) {
-        while (i >= A.off[c + 1]) ++c;
-        const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, A.ch[c].kq, bad));
-        bits = (unsigned long long)__double_as_longlong(sp);
+    unsigned long long reg_acc = 0ull;   // thread 0 only
+    int reg_chan = -1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < A.n_cells; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool active = i < A.n_cells;
+        const int home = find_channel(A.off, A.n_channels, i0);
+        if (threadIdx.x == 0) s_acc = 0ull;
+        __syncthreads();
+        int c = home;
+        unsigned long long bits = 0ull;
+        bool bad = false;
+        if (active) {
+            while (i >= A.off[c + 1]) ++c;
+            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, A.ch[c].kq, bad));
+            bits = (unsigned long long)__double_as_longlong(sp);
+        }
+        raise_flag(A.flags, bad);
+        reduce_channel_max(bits, c, active, home, &s_acc, A.amax);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (home != reg_chan) {
+                if (reg_chan >= 0) atomicMax(&A.amax[reg_chan], reg_acc);
+                reg_chan = home;
+                reg_acc = s_acc;
+            } else {
+                reg_acc = (s_acc > reg_acc) ? s_acc : reg_acc;
+            }
+        }
     }
-    raise_flag(A.flags, bad);
-    reduce_channel_max(bits, c, active, home, &s_acc, A.amax);
-    __syncthreads();
-    if (threadIdx.x == 0) atomicMax(&A.amax[home], s_acc);
+    if (threadIdx.x == 0 && reg_chan >= 0) atomicMax(&A.amax[reg_chan], reg_acc);
 }
 
 template <int G, int PREC>
@@ -245,6 +263,29 @@ static inline unsigned int blocks_for(int64_t n, int bs)
     return (unsigned int)((n + bs - 1) / bs);
 }
 
+// CFL kernel grid: enough workgroups to fill the chip, few enough that the per-workgroup
+// global atomics (serialised on one address per channel) stay cheap.
+static inline unsigned int cfl_grid(int64_t n_cells)
+{
+    const unsigned int full = blocks_for(n_cells, 256);
+    return full < 2048u ? full : 2048u;
+}
+
+template <int PREC>
+static hipError_t launch_fluct_prec(const FluctArgs &a, int G, hipStream_t stream)
+{
+    const dim3 grid(blocks_for(a.n, 256)), block(256);
+    switch (G) {
+    case 1: hipLaunchKernelGGL((k_fluct<1, PREC>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_fluct<2, PREC>), grid, block, 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((k_fluct<3, PREC>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((k_fluct<4, PREC>), grid, block, 0, stream, a); break;
+    case 5: hipLaunchKernelGGL((k_fluct<5, PREC>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int PREC>
 static hipError_t launch_step_prec(const StepArgs &a, int G, int tile, int grid, hipStream_t s)
 {
@@ -260,36 +301,54 @@ static hipError_t launch_step_prec(const StepArgs &a, int G, int tile, int grid,
     return hipGetLastError();
 }
 
+template <int PREC>
+static int occupancy_prec(int G, int tile)
+{
+    int n = 0;
+    const size_t lds = sizeof(double) * 3 * (size_t)tile;
+    hipError_t e = hipErrorInvalidValue;
+    switch (G) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<1, PREC>, tile, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<2, PREC>, tile, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<3, PREC>, tile, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<4, PREC>, tile, lds); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<5, PREC>, tile, lds); break;
+    default: break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int step_blocks_per_cu(int precision, int G, int tile)
+{
+    return precision == PREC_MIXED ? occupancy_prec<PREC_MIXED>(G, tile)
+                                   : occupancy_prec<PREC_FP64>(G, tile);
+}
+
 hipError_t launch_step(const StepArgs &a, int precision, int G, int tile, int grid,
                        hipStream_t stream)
 {
     if (tile < 64 || tile > kMaxTile || (tile & 63) || grid < 1) return hipErrorInvalidValue;
     if (precision == PREC_FP64) return launch_step_prec<PREC_FP64>(a, G, tile, grid, stream);
+    if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED>(a, G, tile, grid, stream);
     return hipErrorNotSupported;
 }
 
 hipError_t launch_cfl(const CflArgs &a, int precision, hipStream_t stream)
 {
     if (a.n_cells < 1) return hipErrorInvalidValue;
-    if (precision != PREC_FP64) return hipErrorNotSupported;
-    hipLaunchKernelGGL((k_cfl<PREC_FP64>), dim3(blocks_for(a.n_cells, 256)), dim3(256), 0, stream, a);
+    const dim3 grid(cfl_grid(a.n_cells)), block(256);
+    if (precision == PREC_FP64) hipLaunchKernelGGL((k_cfl<PREC_FP64>), grid, block, 0, stream, a);
+    else if (precision == PREC_MIXED) hipLaunchKernelGGL((k_cfl<PREC_MIXED>), grid, block, 0, stream, a);
+    else return hipErrorNotSupported;
     return hipGetLastError();
 }
 
 hipError_t launch_fluct(const FluctArgs &a, int precision, int G, hipStream_t stream)
 {
     if (a.n < 1) return hipSuccess;
-    if (precision != PREC_FP64) return hipErrorNotSupported;
-    const dim3 grid(blocks_for(a.n, 256)), block(256);
-    switch (G) {
-    case 1: hipLaunchKernelGGL((k_fluct<1, PREC_FP64>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_fluct<2, PREC_FP64>), grid, block, 0, stream, a); break;
-    case 3: hipLaunchKernelGGL((k_fluct<3, PREC_FP64>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((k_fluct<4, PREC_FP64>), grid, block, 0, stream, a); break;
-    case 5: hipLaunchKernelGGL((k_fluct<5, PREC_FP64>), grid, block, 0, stream, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (precision == PREC_FP64) return launch_fluct_prec<PREC_FP64>(a, G, stream);
+    if (precision == PREC_MIXED) return launch_fluct_prec<PREC_MIXED>(a, G, stream);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_cell_update(const double *Dm, const double *Dp, const double *dt, double,

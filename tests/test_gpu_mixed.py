@@ -1,0 +1,129 @@
+"""Mixed-precision HIP path (FP32 bulk, FP64 near coalescing eigenvalues and for the cell
+accumulation) vs the CPU FP64 oracle, through the C ABI (MI355X).
+
+Bar: relative L1 <= 1e-5 per variable (per channel for batched runs).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04791_amd import inputs
+
+from common import max_rel_l1, oracle_run, per_channel_rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dsve():
+    from paper_1912_04791_amd import dsve as d
+    return d
+
+
+def run_gpu(dsve, wl, steps=None, precision="mixed", launch=None):
+    ctx = dsve.Context.from_workload(wl, precision=precision)
+    if launch is not None:
+        ctx.set_launch(*launch)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, wl.steps if steps is None else steps, t)
+    ctx.sync()
+    out = (h.cpu().numpy(), q.cpu().numpy(), z.cpu().numpy(), t.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def pairwise(dsve, torch, WL, WR, Ag, porosity=0.4, G=3, precision="mixed"):
+    n = WL[0].size
+    ctx = dsve.Context.single(16, porosity=porosity, A_g=Ag, n_gauss=G, dx=1.0,
+                              precision=precision)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (*WL, *WR)]
+    Dm = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    Dp = torch.zeros_like(Dm)
+    ctx.dot_edge_fluct(*dev, Dm, Dp)
+    ctx.sync()
+    ctx.close()
+    return Dm.cpu().numpy(), Dp.cpu().numpy()
+
+
+@pytest.mark.parametrize("G", [1, 3, 5])
+def test_pairwise_fluct_mixed(torch_dev, dsve, G):
+    WL, WR = inputs.make_random_edges(200_000, seed=200 + G)
+    gm, gp = pairwise(dsve, torch_dev, WL, WR, 0.02, G=G)
+    rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, 0.02, G=G)
+    for got, ref in ((gm, rm), (gp, rp)):
+        assert np.abs(got - ref).sum() / np.abs(ref).sum() <= TOL
+
+
+def _near_critical_edges(n, Ag, seed):
+    """Edges whose states sit at Froude numbers in [0.9, 1.1] (eigenvalues close to coalescing
+    when transport is weak)."""
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.2, 2.0, n)
+    Fr = rng.uniform(0.9, 1.1, n)
+    u = Fr * np.sqrt(9.81 * h)
+    hR = h * (1 + 1e-3 * rng.uniform(-1, 1, n))
+    uR = u * (1 + 1e-3 * rng.uniform(-1, 1, n))
+    z = rng.uniform(-0.1, 0.1, n)
+    zR = z + 1e-3 * rng.uniform(-1, 1, n)
+    return (h, h * u, z), (hR, hR * uR, zR)
+
+
+@pytest.mark.parametrize("Ag", [1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
+def test_near_coalescence_stress(torch_dev, dsve, Ag):
+    # Fr in [0.9, 1.1] with weak transport: the two slow eigenvalues nearly coalesce and the
+    # arccos argument is close to 1.  The FP64 band keeps the mixed result at the FP32 level.
+    WL, WR = _near_critical_edges(100_000, Ag, seed=int(-np.log10(Ag)))
+    gm, gp = pairwise(dsve, torch_dev, WL, WR, Ag)
+    rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, Ag)
+    for got, ref in ((gm, rm), (gp, rp)):
+        assert np.abs(got - ref).sum() / np.abs(ref).sum() <= TOL
+
+
+def test_c3_shape_reduced_full_length(torch_dev, dsve):
+    # transcritical flow (Fr 0.33 .. 2.45) for the full 2000 steps at 2^14 cells
+    wl = inputs.make_c3(n_cells=1 << 14)
+    got = run_gpu(dsve, wl)
+    ref = oracle_run(wl)
+    err = max_rel_l1(got, ref)
+    assert err <= TOL, err
+    np.testing.assert_allclose(got[3], ref[3], rtol=1e-6)
+
+
+def test_c2_shape_reduced(torch_dev, dsve):
+    wl = inputs.make_c2(n_cells=1 << 15, steps=400)
+    got = run_gpu(dsve, wl)
+    ref = oracle_run(wl)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+def test_c5_shape_batched_reduced(torch_dev, dsve):
+    wl = inputs.make_c5(n_channels=48, len_lo=512, len_hi=4096, steps=300)
+    got = run_gpu(dsve, wl)
+    ref = oracle_run(wl)
+    per = per_channel_rel_l1(got, ref, wl.offsets)
+    assert per.max() <= TOL, (per.max(), per.argmax())
+
+
+def test_full_size_c3_two_steps_mixed(torch_dev, dsve):
+    wl = inputs.make_c3()
+    got = run_gpu(dsve, wl, steps=2)
+    ref = oracle_run(wl, steps=2)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+def test_mixed_is_deterministic_across_launches(torch_dev, dsve):
+    wl = inputs.make_c5(n_channels=20, len_lo=512, len_hi=2048, steps=25)
+    outs = [run_gpu(dsve, wl, launch=l) for l in [(256, 0, 0), (64, 4, 12), (128, 1, 24)]]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
