@@ -32,17 +32,18 @@ UNIT = "edge-updates/s"
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA)
 FP32_VALU_PEAK_TFLOPS = 78.6   # same rate without packed FP32 (packed FP32 is disabled)
 
-# Algorithmic operation count of one edge update at G = 3 in the form the kernel evaluates
-# (each +, -, *, / and each sqrt, acos, sin, cos counted as one; an FMA as two):
-# per quadrature node 141 (eigenvalues 46, A dW and |A| dW 91, path node 4), per edge
-# 3 x 141 + 15, per cell update 11 plus its CFL speed 48.  Derivation in the design doc.
-OPS_PER_NODE = 141
-OPS_PER_EDGE_EXTRA = 15
-OPS_PER_CELL = 59
+# Algorithmic operation count of one edge update (each +, -, *, / and each sqrt, arccos,
+# cosine counted as one): the matrix-vector form of the DOT fluctuation costs about 150 flops,
+# 9 divisions, 3 square roots, 1 arccos and 3 cosines per quadrature node (166 operations),
+# and each updated cell about 51 for its CFL speed plus 9 for the update.  At G = 3 that is
+# 558 operations per edge update.  A fixed count of the method, not of the kernel's
+# instruction stream (which the VALU counters report separately).
+OPS_PER_NODE = 166
+OPS_PER_CELL = 60
 
 
 def ops_per_edge_update(G: int = 3) -> int:
-    return G * OPS_PER_NODE + OPS_PER_EDGE_EXTRA + OPS_PER_CELL
+    return G * OPS_PER_NODE + OPS_PER_CELL
 
 
 def kernel_source_hash() -> str:
@@ -240,8 +241,15 @@ def main():
     }
     for prec in precisions[1:]:
         r = results[prec]
+        achieved_p = edges * ops / (r["ms_per_step"] * 1e-3) / 1e12
+        peak_p = FP64_VALU_PEAK_TFLOPS if prec == "fp64" else FP32_VALU_PEAK_TFLOPS
         out[prec] = {"value": r["edge_updates_per_s"], "ms_per_step": r["ms_per_step"],
-                     "speedup_vs_" + main_prec: r["edge_updates_per_s"] / main["edge_updates_per_s"]}
+                     "speedup_vs_" + main_prec: r["edge_updates_per_s"] / main["edge_updates_per_s"],
+                     "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
+                                "graph_steps": r["launch"][2]},
+                     "roofline": {"bound": "alu", "achieved": achieved_p, "peak": peak_p,
+                                  "unit": "TFLOP/s", "frac": achieved_p / peak_p,
+                                  "traffic": measured_traffic(wl.name, prec)}}
 
     if not args.no_cpu:
         base, ref, n = cpu_baseline(wl)

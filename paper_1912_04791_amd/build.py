@@ -41,9 +41,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libdsve.so)")
 
 
-def build(verbose: bool = False, extra_device_flags=None) -> str:
-    """Compile every source and link libdsve.so; always recompiles."""
+def build(verbose: bool = False, extra_device_flags=None, out: str | None = None) -> str:
+    """Compile every source and link libdsve.so (or `out`); always recompiles."""
     cc = hipcc()
+    lib = out or LIB
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src, flags in SOURCES.items():
@@ -56,13 +57,13 @@ def build(verbose: bool = False, extra_device_flags=None) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -227,13 +227,13 @@ static void release(dsve_ctx *c)
 }
 
 static ChanInfo make_chan(int64_t cell0, int64_t n, double Ag, double por, double dx, int bcl,
-                          int bcr, double q_in, double cfl)
+                          int bcr, double q_in, double cfl, double g)
 {
     ChanInfo ci{};
     ci.cell0 = cell0;
     ci.ncell = n;
     const double xi = 1.0 / (1.0 - por);
-    ci.kq = 3.0 * xi * Ag;
+    ci.kqg = 3.0 * xi * Ag * g;
     ci.cfl_dx = cfl * dx;
     ci.dx = dx;
     ci.q_in = q_in;
@@ -266,7 +266,7 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
     c->n_cells = n_cells;
     c->h_off = {0, n_cells};
     c->h_ch.push_back(make_chan(0, n_cells, p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right,
-                                p->q_in, p->cfl));
+                                p->q_in, p->cfl, p->g));
     st = setup(c, hip_stream);
     if (st != DSVE_OK) {
         release(c);
@@ -306,7 +306,8 @@ dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *o
     c->h_ch.reserve(n_channels);
     for (int64_t k = 0; k < n_channels; ++k)
         c->h_ch.push_back(make_chan(offsets[k], offsets[k + 1] - offsets[k], A_g[k], porosity[k], dx[k],
-                                    bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, common->cfl));
+                                    bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, common->cfl,
+                                    common->g));
     st = setup(c, hip_stream);
     if (st != DSVE_OK) {
         release(c);
@@ -349,7 +350,7 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
     FluctArgs a{};
     a.hL = hL; a.qL = qL; a.zL = zL; a.hR = hR; a.qR = qR; a.zR = zR;
     a.Dm = Dm; a.Dp = Dp; a.flags = ctx->d_flags; a.n = n;
-    a.g = ctx->g; a.kq = ctx->h_ch[0].kq; a.rule = ctx->rule;
+    a.g = ctx->g; a.kqg = ctx->h_ch[0].kqg; a.rule = ctx->rule;
     HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->stream));
     return DSVE_OK;
 }

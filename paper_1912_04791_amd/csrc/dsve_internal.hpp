@@ -22,12 +22,19 @@ enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 
 constexpr int kMaxGauss = 5;
-constexpr int kMaxTile = 256;
+constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most
+// Waves per SIMD the step kernel is compiled for (bounds its registers per lane).
+#ifndef DSVE_MINW_FP64
+#define DSVE_MINW_FP64 3
+#endif
+#ifndef DSVE_MINW_MIXED
+#define DSVE_MINW_MIXED 4
+#endif
 
 struct alignas(16) ChanInfo {
     int64_t cell0;   // first cell of the channel in the concatenated state
     int64_t ncell;   // N_c
-    double kq;       // 3 xi A_g: xi dq_s/dq = kq u^2 / h and xi dq_s/dh = -kq u^3 / h (Grass)
+    double kqg;      // 3 xi A_g g: xi dq_s/dq = kqg Fr^2 for the Grass law
     double cfl_dx;   // cfl * dx  (dt = cfl_dx / amax)
     double dx;
     double q_in;     // inflow discharge for BC_INFLOW_Q
@@ -75,7 +82,7 @@ struct FluctArgs {
     double *Dm, *Dp;             // [3][n]
     unsigned int *flags;
     int64_t n;
-    double g, kq;
+    double g, kqg;
     GaussRule rule;
 };
 

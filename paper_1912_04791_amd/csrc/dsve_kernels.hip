@@ -62,23 +62,25 @@ __device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
 // Edge fluctuation and cell speed for the chosen precision.
 template <int G, int PREC>
 __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, double hR, double qR,
-                                           double zR, double g, double kq, const GaussRule &rule,
-                                           double Dm[3], double Dp[3], bool &bad)
+                                           double zR, double g, const Closure &K,
+                                           const GaussRule &rule, double Dm[3], double Dp[3],
+                                           bool &bad)
 {
-    if constexpr (PREC == PREC_FP64) fluct64<G>(hL, qL, zL, hR, qR, zR, g, kq, rule, Dm, Dp, bad);
-    else fluct_mixed<G>(hL, qL, zL, hR, qR, zR, g, kq, rule, Dm, Dp, bad);
+    if constexpr (PREC == PREC_FP64) fluct64<G>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    else fluct_mixed<G>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
 }
 
 template <int PREC>
-__device__ __forceinline__ double cell_speed(double h, double q, double g, double kq, bool &bad)
+__device__ __forceinline__ double cell_speed(double h, double q, double g, const Closure &K,
+                                             bool &bad)
 {
-    if constexpr (PREC == PREC_FP64) return speed64(h, q, g, kq, bad);
-    else return speed_mixed(h, q, g, kq, bad);
+    if constexpr (PREC == PREC_FP64) return speed64(h, q, g, K, bad);
+    else return speed_mixed(h, q, g, K, bad);
 }
 
 // ---------------------------------------------------------------------------
 template <int G, int PREC>
-__global__ __launch_bounds__(kMaxTile) void k_step(StepArgs A)
+__global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE_MINW_MIXED) void k_step(StepArgs A)
 {
     extern __shared__ double s_dm[];          // [3][T]
     __shared__ unsigned long long s_acc;
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(kMaxTile) void k_step(StepArgs A)
         if (have_edge)
             while (ge >= A.eoff[c + 1]) ++c;
         const ChanInfo ci = A.ch[c];
+        const Closure K = closure_of(ci.kqg);
         const int64_t e = ge - A.eoff[c];
         bool bad = false;
         double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(kMaxTile) void k_step(StepArgs A)
             if (e == 0 && ci.bcl == BC_INFLOW_Q) qL = ci.q_in;
             double qRe = qR;
             if (e == N && ci.bcr == BC_INFLOW_Q) qRe = ci.q_in;
-            edge_fluct<G, PREC>(hL, qL, zL, hR, qRe, zR, A.g, ci.kq, A.rule, Dm, Dp, bad);
+            edge_fluct<G, PREC>(hL, qL, zL, hR, qRe, zR, A.g, K, A.rule, Dm, Dp, bad);
         }
         s_dm[t] = Dm[0];
         s_dm[T + t] = Dm[1];
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(kMaxTile) void k_step(StepArgs A)
             A.hn[i] = hn;
             A.qn[i] = qn;
             A.zn[i] = zn;
-            const double sp = fabs(cell_speed<PREC>(hn, qn, A.g, ci.kq, bad));
+            const double sp = fabs(cell_speed<PREC>(hn, qn, A.g, K, bad));
             sp_bits = (unsigned long long)__double_as_longlong(sp);
             if (e == 0) {
                 A.t[c] += dt;
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
         bool bad = false;
         if (active) {
             while (i >= A.off[c + 1]) ++c;
-            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, A.ch[c].kq, bad));
+            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, closure_of(A.ch[c].kqg), bad));
             bits = (unsigned long long)__double_as_longlong(sp);
         }
         raise_flag(A.flags, bad);
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
     bool bad = false;
     if (e < A.n) {
         double Dm[3], Dp[3];
-        edge_fluct<G, PREC>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, A.kq, A.rule,
+        edge_fluct<G, PREC>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.kqg), A.rule,
                             Dm, Dp, bad);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {

@@ -1,38 +1,43 @@
 // dsve_math.hpp -- per-node and per-edge arithmetic of the A-DOT hot path (device code).
 //
-// For one state W = (h, q, z) on the segment path (Sec. 3.1, Eq. path):
-//   u = q/h, c^2 = g h, Fr = u/c;
-//   Grass closure (Sec. 2 Eq. Grass; Sec. 3.3 step 1):
-//     b = xi dq_s/dq = 3 xi A_g u^2/h,  a = xi dq_s/dh = -3 xi A_g u^3/h = -b u
-//   cubic parameters (Sec. 3.3, Eqs. parameters, parameters_bis):
-//     k1 = 3 + Fr^2 + 3b,  k2 = -2 Fr^3 + 18 Fr (1 + b) + 27 a / c,  x = k2 / sqrt(4 k1^3),
-//     phi = arccos(x)
-//   eigenvalues (Eq. lambda), theta = phi/3, m = (2/3) c sqrt(k1), f = (2/3) u:
-//     lambda_{1,2} = f - m cos(theta -+ pi/3),  lambda_3 = f + m cos(theta)
-//   where cos(theta -+ pi/3) = cos(theta)/2 +- (sqrt 3/2) sin(theta): one (cos, sin) pair
-//   serves all three roots, and the gaps follow without cancellation:
-//     lambda_2 - lambda_1 = sqrt3 m sin(theta),
-//     lambda_3 - lambda_1 = m (3/2 cos(theta) + sqrt3/2 sin(theta)),
-//     lambda_3 - lambda_2 = m (3/2 cos(theta) - sqrt3/2 sin(theta));
-//   right eigenvectors r_m = [1, lambda_m, (u - lambda_m)^2/c^2 - 1]       (Eq. RR)
-//   left eigenvectors  l_i = [c^2 - u^2 + l_j l_k, 2u - l_j - l_k, c^2] / ((l_i - l_j)(l_i - l_k)),
-//                      (i, j, k) cyclic                                     (Eqs. RR-1, circPerm)
-//   with the three denominators taken from the gap products (one reciprocal for all three).
+// Everything is evaluated in the non-dimensional form the paper uses for the characteristic
+// polynomial (Sec. 3.3, Eq. charPol): eigenvalues are mu_m = lambda_m / c and depend on the
+// Froude number only.  For one state W = (h, q, z):
+//   c = sqrt(g h), Fr = u/c = q / sqrt(g h^3)  (one reciprocal square root gives Fr, c, 1/c);
+//   Grass closure (Sec. 2 Eq. Grass; Sec. 3.3 step 1), with u^2/h = g Fr^2:
+//     b = xi dq_s/dq = 3 xi A_g g Fr^2 = kqg Fr^2,   xi dq_s/dh = -b u;
+//   cubic parameters (Eqs. parameters, parameters_bis), substituting the closure:
+//     k1 = 3 + Fr^2 + 3b           = 3 + Fr^2 (1 + 3 kqg)
+//     k2 = -2Fr^3 + 18Fr(1+b) - 27bFr = Fr (18 - Fr^2 (2 + 9 kqg)),
+//     x = k2 / sqrt(4 k1^3),  phi = arccos(x),  theta = phi/3;
+//   eigenvalues (Eq. lambda), m = (2/3) sqrt(k1), f = (2/3) Fr:
+//     mu_{1,2} = f - m cos(theta -+ pi/3),  mu_3 = f + m cos(theta),
+//   with cos(theta -+ pi/3) = cos(theta)/2 +- (sqrt3/2) sin(theta), so one (cos, sin) pair
+//   serves all three roots and the gaps follow without cancellation:
+//     mu_2 - mu_1 = sqrt3 m sin(theta),  mu_3 - mu_1 = m (3/2 cos + sqrt3/2 sin),
+//     mu_3 - mu_2 = m (3/2 cos - sqrt3/2 sin);
+//   right eigenvectors (Eq. RR):  r_m = [1, c mu_m, (Fr - mu_m)^2 - 1];
+//   left eigenvectors (Eqs. RR-1, circPerm), the factor c^2 of numerator and denominator
+//   cancelling:  l_i . dW = [(1 - Fr^2 + mu_j mu_k) dh + (2Fr - mu_j - mu_k) dq/c + dz]
+//                           / ((mu_i - mu_j)(mu_i - mu_k)),
+//   where 2Fr - mu_j - mu_k = mu_i (the roots sum to the trace, 2Fr), and the three
+//   denominators come from the gap products (one reciprocal for all three).
 // The fluctuation (Sec. 3.1, Eq. DOTjumpN) is accumulated as
-//   S_A = sum_k w_k A(Psi_k) dW   with the explicit flux matrix (Eq. W&A_definition),
-//   S_B = sum_k w_k |A(Psi_k)| dW  with |A| dW = sum_m |lambda_m| (l_m . dW) r_m   (Eqs. asbA, ExAbsA),
+//   S_A = sum_k w_k A(Psi_k) dW   with the explicit flux matrix (Eq. W&A_definition):
+//         A dW = [dq, c^2 ((1 - Fr^2) dh + 2Fr dq/c + dz), b c (dq/c - Fr dh)],
+//   S_B = sum_k w_k |A(Psi_k)| dW  with |A| dW = sum_m c |mu_m| (l_m . dW) r_m   (Eqs. asbA, ExAbsA),
 //   D^- = (S_A - S_B)/2,  D^+ = (S_A + S_B)/2,
-// i.e. |A| is applied to dW as R (|Lambda| (R^-1 dW)) instead of being formed as a 3x3 matrix.
+// i.e. |A| is applied to dW as R (|Lambda| (R^-1 dW)) rather than formed as a 3x3 matrix.
 //
-// Arithmetic kernels used below (own implementations, published methods):
-//   rcp_nr / rsqrt_nr: hardware reciprocal / reciprocal-square-root estimate refined by two
-//     Newton-Raphson steps (quadratic convergence).
-//   trisect: cos(theta), sin(theta) with theta = arccos(x)/3.  An FP32 estimate of theta
-//     (arccos, then sine/cosine) gives a point on the unit circle, renormalised in FP64; the
-//     residual angle follows from the complex identity  Im(w conj(z)^3) = sin(phi - 3 theta0),
-//     w = x + i sqrt(1-x^2), z = cos(theta0) + i sin(theta0), and a rotation by that residual/3
-//     (second-order sine/cosine of a small angle) removes it.  Each correction leaves an
-//     error of order (residual)^3.
+// Arithmetic kernels (own implementations of published methods):
+//   rcp_h / rsqrt_h: hardware reciprocal / reciprocal-square-root estimate (about 2^-24
+//     relative) refined by one Halley step (cubic convergence, about 2^-72).
+//   trisect: cos(theta), sin(theta), theta = arccos(x)/3.  An FP32 estimate of theta gives a
+//     point on the unit circle, renormalised in FP64; the residual angle follows from the
+//     complex identity Im(w conj(z)^3) = sin(phi - 3 theta0), w = x + i sqrt(1 - x^2),
+//     z = cos(theta0) + i sin(theta0), and a rotation by residual/3 (second-order sine and
+//     cosine of a small angle) removes it; each correction leaves an error of order
+//     (residual)^3.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,9 +48,8 @@
 
 namespace dsve {
 
-constexpr double kSqrt3 = 1.73205080756887729352744634150587237;
 constexpr double kSqrt3Half = 0.86602540378443864676372317075293618;
-constexpr double kAcosTol = 1e-12;      // tolerance on |arccos argument| - 1 before flagging
+constexpr double kAcosTol = 1e-12;            // tolerance on |arccos argument| - 1 before flagging
 constexpr double kTrisectTwoRounds = 0.984;   // |x| above which the FP32 estimate gets two rounds
 constexpr float kMixedFp64Band = 1e-3f;       // mixed form: 1 - |x| below this -> FP64 node
 
@@ -59,34 +63,29 @@ __device__ __forceinline__ float clamp_unitf(float x)
     return (x > 1.0f) ? 1.0f : ((x < -1.0f) ? -1.0f : x);
 }
 
-__device__ __forceinline__ double rcp_nr(double x)
+// 1/x: r (1 + e + e^2), e = 1 - x r
+__device__ __forceinline__ double rcp_h(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 
-__device__ __forceinline__ double rsqrt_nr(double x)
+// 1/sqrt(x): r (1 + e/2 + 3e^2/8), e = 1 - x r^2
+__device__ __forceinline__ double rsqrt_h(double x)
 {
-    double r = __builtin_amdgcn_rsq(x);
-    // r <- r (1 + e/2), e = 1 - x r^2
-    double e = fma(-x * r, r, 1.0);
-    r = fma(0.5 * r, e, r);
-    e = fma(-x * r, r, 1.0);
-    return fma(0.5 * r, e, r);
+    const double r = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * r, r, 1.0);
+    return fma(r * e, fma(e, 0.375, 0.5), r);
 }
 
 // One correction of (c, s) ~ (cos theta, sin theta) towards 3 theta = phi, cos(phi) = x,
-// sin(phi) = y >= 0; (c, s) must be unit length to rounding.
+// sin(phi) = y >= 0; (c, s) unit length to rounding.
 __device__ __forceinline__ void trisect_correct(double x, double y, double &c, double &s)
 {
-    const double c2 = c * c, s2 = s * s;
-    const double C3 = c * fma(4.0, c2, -3.0);      // cos(3 theta0)
-    const double S3 = s * fma(-4.0, s2, 3.0);      // sin(3 theta0)
-    const double res = fma(y, C3, -x * S3);        // sin(phi - 3 theta0)
-    const double d = res * (1.0 / 3.0);
+    const double C3 = c * fma(4.0 * c, c, -3.0);   // cos(3 theta0)
+    const double S3 = s * fma(-4.0 * s, s, 3.0);   // sin(3 theta0)
+    const double d = fma(y, C3, -x * S3) * (1.0 / 3.0);   // sin(phi - 3 theta0) / 3
     const double cd = fma(-0.5 * d, d, 1.0);
     const double cn = fma(c, cd, -s * d);
     const double sn = fma(s, cd, c * d);
@@ -94,14 +93,14 @@ __device__ __forceinline__ void trisect_correct(double x, double y, double &c, d
     s = sn;
 }
 
-// (cos theta, sin theta), theta = arccos(x) / 3, for x in [-1, 1] (NaN propagates).
+// (cos theta, sin theta), theta = arccos(x) / 3, x in [-1, 1] (NaN propagates).
 __device__ __forceinline__ void trisect(double x, double &c, double &s)
 {
-    const double v = (1.0 - x) * (1.0 + x);
-    const double y = (v > 0.0) ? v * rsqrt_nr(v) : (v == 0.0 ? 0.0 : v);   // sin(phi)
+    const double v = fma(-x, x, 1.0);
+    const double y = (v > 0.0) ? v * rsqrt_h(v) : (v == 0.0 ? 0.0 : v);   // sin(phi)
     const float th0 = acosf((float)x) * (1.0f / 3.0f);
     const double c0 = (double)__cosf(th0), s0 = (double)__sinf(th0);
-    // renormalise: r = 1 / sqrt(c0^2 + s0^2) to second order in e = c0^2 + s0^2 - 1 (|e| ~ 1e-7)
+    // renormalise: 1/sqrt(c0^2 + s0^2) to second order in e = c0^2 + s0^2 - 1 (|e| ~ 1e-7)
     const double e = fma(c0, c0, fma(s0, s0, -1.0));
     const double nr = fma(e, fma(e, 0.375, -0.5), 1.0);
     c = c0 * nr;
@@ -111,93 +110,98 @@ __device__ __forceinline__ void trisect(double x, double &c, double &s)
 }
 
 // ---------------------------------------------------------------------------
-// FP64 eigenvalues at one state, with what the eigenvectors need.
+// Per-channel constants of the closure: kqg = 3 xi A_g g, K1 = 1 + 3 kqg, K2 = 2 + 9 kqg.
+struct Closure {
+    double kqg, K1, K2;
+};
+__device__ __forceinline__ Closure closure_of(double kqg)
+{
+    return Closure{kqg, fma(3.0, kqg, 1.0), fma(9.0, kqg, 2.0)};
+}
+
+// FP64 non-dimensional eigenstructure at one state.
 struct Eig64 {
-    double u, c2, inv_c2, a, b;
-    double l1, l2, l3;
-    double g21, g31, g32;   // lambda_2 - lambda_1, lambda_3 - lambda_1, lambda_3 - lambda_2
+    double Fr, c, inv_c, b;
+    double mu1, mu2, mu3;
+    double g21, g31, g32;   // mu_2 - mu_1, mu_3 - mu_1, mu_3 - mu_2
 };
 
-__device__ __forceinline__ void eig64(double h, double q, double g, double kq, Eig64 &E, bool &bad)
+__device__ __forceinline__ void eig64(double h, double q, double g, const Closure &K, Eig64 &E,
+                                      bool &bad)
 {
-    const double inv_h = rcp_nr(h);
-    const double u = q * inv_h;
-    const double c2 = g * h;
-    const double inv_c = rsqrt_nr(c2);
-    const double c = c2 * inv_c;
-    const double Fr = u * inv_c;
-    const double b = kq * u * u * inv_h;   // xi dq_s/dq
-    const double a = -b * u;               // xi dq_s/dh
+    const double gh = g * h;
+    const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
+    const double Fr = q * t;
+    const double inv_c = h * t;
     const double Fr2 = Fr * Fr;
-    const double k1 = 3.0 + Fr2 + 3.0 * b;
-    const double k2 = Fr * (18.0 * (1.0 + b) - 2.0 * Fr2) + 27.0 * a * inv_c;
-    const double r1 = rsqrt_nr(k1);
-    const double s1 = k1 * r1;                       // sqrt(k1)
-    double x = 0.5 * k2 * (r1 * r1 * r1);            // k2 / sqrt(4 k1^3)
+    const double k1 = fma(Fr2, K.K1, 3.0);
+    const double k2 = Fr * fma(-Fr2, K.K2, 18.0);
+    const double r1 = rsqrt_h(k1);
+    double x = (0.5 * k2) * (r1 * r1 * r1);   // k2 / sqrt(4 k1^3)
     bad |= isfinite(k1) && isfinite(k2) && (!(k1 > 0.0) || fabs(x) > 1.0 + kAcosTol);
     x = clamp_unit(x);
     double cs, sn;
     trisect(x, cs, sn);
-    const double m = (2.0 / 3.0) * s1 * c;
-    const double f = (2.0 / 3.0) * u;
+    const double m = (2.0 / 3.0) * (k1 * r1);
+    const double f = (2.0 / 3.0) * Fr;
     const double p = 0.5 * cs, r = kSqrt3Half * sn;
-    E.u = u;
-    E.c2 = c2;
-    E.inv_c2 = inv_c * inv_c;
-    E.a = a;
-    E.b = b;
-    E.l1 = f - m * (p + r);
-    E.l2 = f - m * (p - r);
-    E.l3 = f + m * cs;
-    E.g21 = m * (kSqrt3 * sn);
-    E.g31 = m * (3.0 * p + r);
-    E.g32 = m * (3.0 * p - r);
+    E.Fr = Fr;
+    E.c = gh * inv_c;
+    E.inv_c = inv_c;
+    E.b = K.kqg * Fr2;
+    E.mu1 = f - m * (p + r);
+    E.mu2 = f - m * (p - r);
+    E.mu3 = fma(m, cs, f);
+    E.g21 = (2.0 * m) * r;
+    E.g31 = m * fma(3.0, p, r);
+    E.g32 = m * fma(3.0, p, -r);
 }
 
 // Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).
-__device__ __forceinline__ double speed64(double h, double q, double g, double kq, bool &bad)
+__device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, bool &bad)
 {
     Eig64 E;
-    eig64(h, q, g, kq, E, bad);
-    return fmax(fmax(fabs(E.l1), fabs(E.l2)), fabs(E.l3));
+    eig64(h, q, g, K, E, bad);
+    return E.c * fmax(fmax(fabs(E.mu1), fabs(E.mu2)), fabs(E.mu3));
 }
 
 // Accumulate one quadrature node: SA += w A dW, SB += w |A| dW.
 __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, double dh, double dq,
                                                   double dz, double SA[3], double SB[3])
 {
-    const double u = E.u, c2 = E.c2;
-    const double l1 = E.l1, l2 = E.l2, l3 = E.l3;
-    // A dW with the explicit flux matrix; row 0 is dq
-    const double base = c2 - u * u;
-    const double tu = 2.0 * u;
-    const double c2dz = c2 * dz;
-    const double A1 = base * dh + tu * dq + c2dz;
-    const double A2 = E.a * dh + E.b * dq;
-    // 1/d_i from the gap products: d1 = g21 g31, d2 = -g21 g32, d3 = g31 g32
-    const double invP = rcp_nr(E.g21 * E.g31 * E.g32);
-    const double id1 = E.g32 * invP, id2 = -E.g31 * invP, id3 = E.g21 * invP;
-    // (R^-1 dW)_i = l_i . dW, scaled by w |lambda_i|
-    const double al1 = ((base + l2 * l3) * dh + (tu - l2 - l3) * dq + c2dz) * id1;
-    const double al2 = ((base + l3 * l1) * dh + (tu - l3 - l1) * dq + c2dz) * id2;
-    const double al3 = ((base + l1 * l2) * dh + (tu - l1 - l2) * dq + c2dz) * id3;
-    const double b1 = w * fabs(l1) * al1, b2 = w * fabs(l2) * al2, b3 = w * fabs(l3) * al3;
-    const double e1 = u - l1, e2 = u - l2, e3 = u - l3;
-    const double r1 = e1 * e1 * E.inv_c2 - 1.0;
-    const double r2 = e2 * e2 * E.inv_c2 - 1.0;
-    const double r3 = e3 * e3 * E.inv_c2 - 1.0;
-    SA[0] += w * dq;
-    SA[1] += w * A1;
-    SA[2] += w * A2;
-    SB[0] += b1 + b2 + b3;
-    SB[1] += b1 * l1 + b2 * l2 + b3 * l3;
-    SB[2] += b1 * r1 + b2 * r2 + b3 * r3;
+    const double Fr = E.Fr, c = E.c;
+    const double mu1 = E.mu1, mu2 = E.mu2, mu3 = E.mu3;
+    const double dqn = dq * E.inv_c;
+    const double base = fma(-Fr, Fr, 1.0);   // (c^2 - u^2) / c^2
+    // explicit A dW (row 0 is dq)
+    const double A1n = fma(base, dh, fma(2.0 * Fr, dqn, dz));
+    const double A2n = E.b * fma(-Fr, dh, dqn);
+    // numerators of l_i . dW (non-dimensional)
+    const double n1 = fma(fma(mu2, mu3, base), dh, fma(mu1, dqn, dz));
+    const double n2 = fma(fma(mu3, mu1, base), dh, fma(mu2, dqn, dz));
+    const double n3 = fma(fma(mu1, mu2, base), dh, fma(mu3, dqn, dz));
+    // w |mu_i| (l_i . dW), denominators 1/d_1 = g32/P, 1/d_2 = -g31/P, 1/d_3 = g21/P
+    const double wP = w * rcp_h(E.g21 * E.g31 * E.g32);
+    const double b1 = n1 * (fabs(mu1) * E.g32) * wP;
+    const double b2 = -n2 * (fabs(mu2) * E.g31) * wP;
+    const double b3 = n3 * (fabs(mu3) * E.g21) * wP;
+    const double e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
+    const double B0 = b1 + b2 + b3;
+    const double B1 = fma(b1, mu1, fma(b2, mu2, b3 * mu3));
+    const double B2 = fma(b1, fma(e1, e1, -1.0), fma(b2, fma(e2, e2, -1.0), b3 * fma(e3, e3, -1.0)));
+    const double wc = w * c;
+    SA[0] = fma(w, dq, SA[0]);
+    SA[1] = fma(wc * c, A1n, SA[1]);
+    SA[2] = fma(wc, A2n, SA[2]);
+    SB[0] = fma(c, B0, SB[0]);
+    SB[1] = fma(c * c, B1, SB[1]);
+    SB[2] = fma(c, B2, SB[2]);
 }
 
 // DOT fluctuations of one edge, FP64 throughout.
 template <int G>
 __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double hR, double qR,
-                                        double zR, double g, double kq, const GaussRule &rule,
+                                        double zR, double g, const Closure &K, const GaussRule &rule,
                                         double Dm[3], double Dp[3], bool &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
@@ -206,7 +210,7 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
     for (int k = 0; k < G; ++k) {
         const double s = rule.s[k];
         Eig64 E;
-        eig64(hL + s * dh, qL + s * dq, g, kq, E, bad);
+        eig64(fma(s, dh, hL), fma(s, dq, qL), g, K, E, bad);
         node_accumulate64(E, rule.w[k], dh, dq, dz, SA, SB);
     }
 #pragma unroll
@@ -221,100 +225,94 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 // kMixedFp64Band of +-1 (coalescing eigenvalues: Fr near +-1 with weak transport) is redone
 // in FP64 from the FP64 path state.  The jumps dW are formed in FP64 and rounded once.
 struct EigF {
-    float u, c2, inv_c2, a, b;
-    float l1, l2, l3;
+    float Fr, c, inv_c, b;
+    float mu1, mu2, mu3;
     float g21, g31, g32;
 };
 
-// Returns false when the node must be evaluated in FP64.
-__device__ __forceinline__ bool eigf(float h, float q, float g, float kq, EigF &E, bool &bad)
+// Returns false when the node must be evaluated in FP64 (the FP32 argument only selects
+// the band, a width of 1e-3 far wider than FP32 rounding; it never decides a result there).
+__device__ __forceinline__ bool eigf(float h, float q, float g, float kqg, float K1, float K2, EigF &E)
 {
-    const float inv_h = __builtin_amdgcn_rcpf(h);
-    const float u = q * inv_h;
-    const float c2 = g * h;
-    const float inv_c = __builtin_amdgcn_rsqf(c2);
-    const float c = c2 * inv_c;
-    const float Fr = u * inv_c;
-    const float b = kq * u * u * inv_h;
-    const float a = -b * u;
+    const float gh = g * h;
+    const float t = __builtin_amdgcn_rsqf(gh * h * h);
+    const float Fr = q * t;
+    const float inv_c = h * t;
     const float Fr2 = Fr * Fr;
-    const float k1 = 3.0f + Fr2 + 3.0f * b;
-    const float k2 = Fr * (18.0f * (1.0f + b) - 2.0f * Fr2) + 27.0f * a * inv_c;
+    const float k1 = fmaf(Fr2, K1, 3.0f);
+    const float k2 = Fr * fmaf(-Fr2, K2, 18.0f);
     const float r1 = __builtin_amdgcn_rsqf(k1);
-    const float s1 = k1 * r1;
-    float x = 0.5f * k2 * (r1 * r1 * r1);
-    // the FP32 argument decides only whether to switch to FP64 (a band of width 1e-3 around
-    // +-1, far wider than FP32 rounding), never the result near the band
+    float x = (0.5f * k2) * (r1 * r1 * r1);
     if (!(fabsf(x) < 1.0f - kMixedFp64Band)) return false;
-    (void)bad;
-    x = clamp_unitf(x);
     const float th = acosf(x) * (1.0f / 3.0f);
     const float cs = __cosf(th), sn = __sinf(th);
-    const float m = (2.0f / 3.0f) * s1 * c;
-    const float f = (2.0f / 3.0f) * u;
+    const float m = (2.0f / 3.0f) * (k1 * r1);
+    const float f = (2.0f / 3.0f) * Fr;
     const float p = 0.5f * cs, r = (float)kSqrt3Half * sn;
-    E.u = u;
-    E.c2 = c2;
-    E.inv_c2 = inv_c * inv_c;
-    E.a = a;
-    E.b = b;
-    E.l1 = f - m * (p + r);
-    E.l2 = f - m * (p - r);
-    E.l3 = f + m * cs;
-    E.g21 = m * ((float)kSqrt3 * sn);
-    E.g31 = m * (3.0f * p + r);
-    E.g32 = m * (3.0f * p - r);
+    E.Fr = Fr;
+    E.c = gh * inv_c;
+    E.inv_c = inv_c;
+    E.b = kqg * Fr2;
+    E.mu1 = f - m * (p + r);
+    E.mu2 = f - m * (p - r);
+    E.mu3 = fmaf(m, cs, f);
+    E.g21 = (2.0f * m) * r;
+    E.g31 = m * fmaf(3.0f, p, r);
+    E.g32 = m * fmaf(3.0f, p, -r);
     return true;
 }
 
 __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float dh, float dq, float dz,
                                                  float SA[3], float SB[3])
 {
-    const float u = E.u, c2 = E.c2;
-    const float l1 = E.l1, l2 = E.l2, l3 = E.l3;
-    const float base = c2 - u * u;
-    const float tu = 2.0f * u;
-    const float c2dz = c2 * dz;
-    const float A1 = base * dh + tu * dq + c2dz;
-    const float A2 = E.a * dh + E.b * dq;
-    const float invP = __builtin_amdgcn_rcpf(E.g21 * E.g31 * E.g32);
-    const float id1 = E.g32 * invP, id2 = -E.g31 * invP, id3 = E.g21 * invP;
-    const float al1 = ((base + l2 * l3) * dh + (tu - l2 - l3) * dq + c2dz) * id1;
-    const float al2 = ((base + l3 * l1) * dh + (tu - l3 - l1) * dq + c2dz) * id2;
-    const float al3 = ((base + l1 * l2) * dh + (tu - l1 - l2) * dq + c2dz) * id3;
-    const float b1 = w * fabsf(l1) * al1, b2 = w * fabsf(l2) * al2, b3 = w * fabsf(l3) * al3;
-    const float e1 = u - l1, e2 = u - l2, e3 = u - l3;
-    const float r1 = e1 * e1 * E.inv_c2 - 1.0f;
-    const float r2 = e2 * e2 * E.inv_c2 - 1.0f;
-    const float r3 = e3 * e3 * E.inv_c2 - 1.0f;
-    SA[0] += w * dq;
-    SA[1] += w * A1;
-    SA[2] += w * A2;
-    SB[0] += b1 + b2 + b3;
-    SB[1] += b1 * l1 + b2 * l2 + b3 * l3;
-    SB[2] += b1 * r1 + b2 * r2 + b3 * r3;
+    const float Fr = E.Fr, c = E.c;
+    const float mu1 = E.mu1, mu2 = E.mu2, mu3 = E.mu3;
+    const float dqn = dq * E.inv_c;
+    const float base = fmaf(-Fr, Fr, 1.0f);
+    const float A1n = fmaf(base, dh, fmaf(2.0f * Fr, dqn, dz));
+    const float A2n = E.b * fmaf(-Fr, dh, dqn);
+    const float n1 = fmaf(fmaf(mu2, mu3, base), dh, fmaf(mu1, dqn, dz));
+    const float n2 = fmaf(fmaf(mu3, mu1, base), dh, fmaf(mu2, dqn, dz));
+    const float n3 = fmaf(fmaf(mu1, mu2, base), dh, fmaf(mu3, dqn, dz));
+    const float wP = w * __builtin_amdgcn_rcpf(E.g21 * E.g31 * E.g32);
+    const float b1 = n1 * (fabsf(mu1) * E.g32) * wP;
+    const float b2 = -n2 * (fabsf(mu2) * E.g31) * wP;
+    const float b3 = n3 * (fabsf(mu3) * E.g21) * wP;
+    const float e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
+    const float B0 = b1 + b2 + b3;
+    const float B1 = fmaf(b1, mu1, fmaf(b2, mu2, b3 * mu3));
+    const float B2 = fmaf(b1, fmaf(e1, e1, -1.0f), fmaf(b2, fmaf(e2, e2, -1.0f), b3 * fmaf(e3, e3, -1.0f)));
+    const float wc = w * c;
+    SA[0] = fmaf(w, dq, SA[0]);
+    SA[1] = fmaf(wc * c, A1n, SA[1]);
+    SA[2] = fmaf(wc, A2n, SA[2]);
+    SB[0] = fmaf(c, B0, SB[0]);
+    SB[1] = fmaf(c * c, B1, SB[1]);
+    SB[2] = fmaf(c, B2, SB[2]);
 }
 
 template <int G>
 __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, double hR, double qR,
-                                            double zR, double g, double kq, const GaussRule &rule,
-                                            double Dm[3], double Dp[3], bool &bad)
+                                            double zR, double g, const Closure &K,
+                                            const GaussRule &rule, double Dm[3], double Dp[3],
+                                            bool &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     const float dhf = (float)dh, dqf = (float)dq, dzf = (float)dz;
-    const float gf = (float)g, kqf = (float)kq;
+    const float hLf = (float)hL, qLf = (float)qL;
+    const float gf = (float)g, kqgf = (float)K.kqg, K1f = (float)K.K1, K2f = (float)K.K2;
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
     double SA64[3] = {0.0, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-        const double s = rule.s[k];
-        const double h = hL + s * dh, q = qL + s * dq;
+        const float sf = (float)rule.s[k];
         EigF E;
-        if (eigf((float)h, (float)q, gf, kqf, E, bad)) {
+        if (eigf(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, kqgf, K1f, K2f, E)) {
             node_accumulatef(E, (float)rule.w[k], dhf, dqf, dzf, SA, SB);
         } else {
+            const double s = rule.s[k];
             Eig64 E64;
-            eig64(h, q, g, kq, E64, bad);
+            eig64(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, bad);
             node_accumulate64(E64, rule.w[k], dh, dq, dz, SA64, SB64);
         }
     }
@@ -326,12 +324,13 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     }
 }
 
-__device__ __forceinline__ double speed_mixed(double h, double q, double g, double kq, bool &bad)
+__device__ __forceinline__ double speed_mixed(double h, double q, double g, const Closure &K,
+                                              bool &bad)
 {
     EigF E;
-    if (eigf((float)h, (float)q, (float)g, (float)kq, E, bad))
-        return (double)fmaxf(fmaxf(fabsf(E.l1), fabsf(E.l2)), fabsf(E.l3));
-    return speed64(h, q, g, kq, bad);
+    if (eigf((float)h, (float)q, (float)g, (float)K.kqg, (float)K.K1, (float)K.K2, E))
+        return (double)(E.c * fmaxf(fmaxf(fabsf(E.mu1), fabsf(E.mu2)), fabsf(E.mu3)));
+    return speed64(h, q, g, K, bad);
 }
 
 }  // namespace dsve

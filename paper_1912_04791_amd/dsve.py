@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdsve.so")
+LIB_PATH = os.environ.get("DSVE_LIBRARY") or os.path.join(_HERE, "libdsve.so")
 
 OK = 0
 E_ARG = -1
