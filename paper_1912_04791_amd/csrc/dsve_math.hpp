@@ -53,6 +53,14 @@ constexpr double kAcosTol = 1e-12;            // tolerance on |arccos argument| 
 constexpr double kTrisectTwoRounds = 0.984;   // |x| above which the FP32 estimate gets two rounds
 constexpr float kMixedFp64Band = 1e-3f;       // mixed form: 1 - |x| below this -> FP64 node
 
+// Unrolling of the quadrature-node loop (independent nodes interleave for ILP when unrolled;
+// a rolled loop needs fewer registers).
+#ifndef DSVE_NODE_UNROLL
+#define DSVE_NODE_UNROLL 8
+#endif
+#define DSVE_PRAGMA(x) _Pragma(#x)
+#define DSVE_UNROLL(n) DSVE_PRAGMA(unroll n)
+
 // Clamp to [-1, 1] keeping NaN (a NaN argument must stay visible downstream).
 __device__ __forceinline__ double clamp_unit(double x)
 {
@@ -206,7 +214,7 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     double SA[3] = {0.0, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
-#pragma unroll
+    DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const double s = rule.s[k];
         Eig64 E;
@@ -303,7 +311,7 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     const float gf = (float)g, kqgf = (float)K.kqg, K1f = (float)K.K1, K2f = (float)K.K2;
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
     double SA64[3] = {0.0, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
-#pragma unroll
+    DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const float sf = (float)rule.s[k];
         EigF E;

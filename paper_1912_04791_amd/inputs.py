@@ -11,8 +11,9 @@ Workloads (all synthetic; the paper's own test data are not used):
   right (1.0, 0.3, 0.2), A_g = 0.01, porosity 0.4, transmissive, 200 steps.
   Shaped like the paper's movable-bed Riemann test (Sec. 4.1).
 * ``c2`` -- one periodic channel, N = 2^20, L = 1000 m, h = 1 + 0.1 sin(2 pi k x / L)
-  with k drawn from {1..8}, u = 0.4 + 0.05 n(x) where n is unit-variance Gaussian
-  noise low-passed to Fourier modes |m| <= 64, z = 0.05 cos(2 pi x / L),
+  with k drawn from {1..8}, u = 0.4 + 0.05 n(x) where n is unit-variance periodic Gaussian
+  noise limited to Fourier modes 0..64 (a random Fourier series with complex Gaussian
+  coefficients, mean removed), z = 0.05 cos(2 pi x / L),
   A_g = 0.005, porosity 0.4, 1000 steps.
 * ``c3`` -- transcritical flow over a Gaussian bed bump, N = 2^24, L = 100 m,
   z = 0.2 exp(-((x-50)/5)^2), q = 0.5, h the frictionless Bernoulli profile
@@ -141,14 +142,24 @@ def make_c1(n_cells: int = 250, steps: int = 200) -> Workload:
                    0.0, steps, meta={"L": L})
 
 
-def _lowpass_noise(rng: np.random.Generator, n: int, max_mode: int) -> np.ndarray:
-    """Unit-std Gaussian noise keeping only Fourier modes |m| <= max_mode (periodic)."""
-    noise = rng.standard_normal(n)
-    spec = np.fft.rfft(noise)
-    spec[max_mode + 1:] = 0.0
-    out = np.fft.irfft(spec, n)
-    sd = out.std()
-    return out / sd if sd > 0 else out
+def _fourier_noise(coefs: np.ndarray, n: int) -> np.ndarray:
+    """Rows of sum_{m=0..M} Re(c_m exp(2 pi i m x)), x = (j + 1/2)/n, each rescaled to unit
+    standard deviation: periodic Gaussian noise limited to Fourier modes m <= M."""
+    coefs = np.atleast_2d(coefs)
+    x = (np.arange(n, dtype=np.float64) + 0.5) / n
+    z = np.exp(2j * np.pi * x)
+    zm = np.ones(n, dtype=np.complex128)
+    out = np.zeros((coefs.shape[0], n))
+    for m in range(coefs.shape[1]):
+        out += (coefs[:, m:m + 1] * zm[None, :]).real
+        zm = zm * z
+    out -= out.mean(axis=1, keepdims=True)
+    sd = out.std(axis=1, keepdims=True)
+    return out / np.where(sd > 0, sd, 1.0)
+
+
+def _noise_coefs(rng: np.random.Generator, max_mode: int) -> np.ndarray:
+    return rng.standard_normal(max_mode + 1) + 1j * rng.standard_normal(max_mode + 1)
 
 
 def smooth_periodic_state(rng: np.random.Generator, n: int, length: float, max_mode: int):
@@ -156,7 +167,7 @@ def smooth_periodic_state(rng: np.random.Generator, n: int, length: float, max_m
     x = cell_centres(n, length)
     k = int(rng.integers(1, 9))
     h = 1.0 + 0.1 * np.sin(2.0 * np.pi * k * x / length)
-    u = 0.4 + 0.05 * _lowpass_noise(rng, n, max_mode)
+    u = 0.4 + 0.05 * _fourier_noise(_noise_coefs(rng, max_mode), n)[0]
     z = 0.05 * np.cos(2.0 * np.pi * x / length)
     return h, h * u, z, k
 
@@ -258,20 +269,33 @@ def make_c5(n_channels: int = 65536, len_lo: int = 512, len_hi: int = 4096, step
     por = top.uniform(0.3, 0.45, n_channels)
     kind = top.permutation(np.arange(n_channels) % 2)  # 0 smooth, 1 Riemann
     children = ss.spawn(n_channels + 1)[1:]
-    parts, dx, bcl = [], np.zeros(n_channels), np.zeros(n_channels, dtype=np.int32)
+    parts = [None] * n_channels
+    dx, bcl = np.zeros(n_channels), np.zeros(n_channels, dtype=np.int32)
+    smooth_k, smooth_coefs = {}, {}
     for c in range(n_channels):
         rng = np.random.default_rng(children[c])
         n = int(lens[c])
         if kind[c] == 0:
-            Lc = n * 1000.0 / float(1 << 20)
-            h, q, z, _ = smooth_periodic_state(rng, n, Lc, max_mode=8)
-            parts.append((h, q, z))
-            dx[c] = Lc / n
+            # same draws, in the same order, as smooth_periodic_state (k, then the coefficients)
+            smooth_k[c] = int(rng.integers(1, 9))
+            smooth_coefs[c] = _noise_coefs(rng, 8)
+            dx[c] = (n * 1000.0 / float(1 << 20)) / n
             bcl[c] = BC_PERIODIC
         else:
-            parts.append(riemann_state(rng, n))
+            parts[c] = riemann_state(rng, n)
             dx[c] = 0.04
             bcl[c] = BC_TRANSMISSIVE
+    # smooth channels, synthesised in groups of equal length
+    smooth = np.array(sorted(smooth_k), dtype=np.int64)
+    for n in np.unique(lens[smooth]) if smooth.size else []:
+        grp = smooth[lens[smooth] == n]
+        noise = _fourier_noise(np.stack([smooth_coefs[c] for c in grp]), int(n))
+        Lc = n * 1000.0 / float(1 << 20)
+        x = cell_centres(int(n), Lc)
+        z = 0.05 * np.cos(2.0 * np.pi * x / Lc)
+        for j, c in enumerate(grp):
+            h = 1.0 + 0.1 * np.sin(2.0 * np.pi * smooth_k[c] * x / Lc)
+            parts[c] = (h, h * (0.4 + 0.05 * noise[j]), z.copy())
     return _assemble("c5", parts, dx, Ag, por, bcl, bcl.copy(), steps, seed, precision="mixed",
                      meta={"kind": kind})
 
@@ -301,3 +325,16 @@ def make_random_edges(n: int, seed: int = 11, h_range=(0.05, 5.0), u_range=(-3.0
 
 
 MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
+
+DESCRIPTIONS = {
+    "c1": "c1: Riemann problem on [0, 10] m, N=250, A_g=0.01, porosity 0.4, G=3, CFL 0.9, "
+          "transmissive, 200 steps",
+    "c2": "c2: periodic single channel, N=2^20 cells, L=1000 m, smooth seeded state, "
+          "A_g=0.005, porosity 0.4, G=3, CFL 0.9, 1000 steps",
+    "c3": "c3: transcritical flow over a bed bump, N=2^24 cells, L=100 m, q=0.5, "
+          "Fr 0.33-2.46, A_g=0.001, porosity 0.4, G=3, CFL 0.9, 2000 steps",
+    "c4": "c4: 4096 channels, lengths log-uniform in [256, 65536] (4.8e7 cells), seeded "
+          "Riemann states, per-channel A_g and porosity, G=3, CFL 0.9, 500 steps",
+    "c5": "c5: 65536 channels, lengths uniform in [512, 4096] (1.5e8 cells), half smooth "
+          "periodic, half Riemann, per-channel A_g and porosity, G=3, CFL 0.9, 5000 steps",
+}

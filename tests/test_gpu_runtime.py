@@ -1,0 +1,147 @@
+"""Runtime pieces of the HIP path on the MI355X: autotuner and its cache, HIP-graph reuse
+and re-capture, streams, full-size batched runs checked on sampled channels.
+
+Channels are independent, so comparing whole channels of a full-size batched run with the
+oracle run on just those channels is exact sampling.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04791_amd import inputs
+
+from common import max_rel_l1, oracle_run, per_channel_rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dsve():
+    from paper_1912_04791_amd import dsve as d
+    return d
+
+
+def to_np(*ts):
+    return tuple(t.cpu().numpy() for t in ts)
+
+
+def test_autotune_keeps_results_and_writes_cache(torch_dev, dsve, tmp_path):
+    wl = inputs.make_c4(n_channels=24, len_lo=200, len_hi=6000, steps=30)
+    cache = str(tmp_path / "tune.json")
+    ref_ctx = dsve.Context.from_workload(wl)
+    h0, q0, z0, t0 = dsve.upload(wl)
+    ref_ctx.adot_step(h0, q0, z0, wl.steps, t0)
+    ref_ctx.sync()
+
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    before = [x.clone() for x in (h, q, z)]
+    ctx.autotune(h, q, z, trial_steps=4, cache_path=cache)
+    # the caller's arrays are read, never written
+    for a, b in zip(before, (h, q, z)):
+        assert torch_dev.equal(a, b)
+    launch = ctx.get_launch()
+    assert launch[0] in (64, 128, 256) and 0 <= launch[1] <= 32
+    lines = [json.loads(l) for l in open(cache).read().splitlines() if l.strip()]
+    assert len(lines) == 1 and lines[0]["tile"] == launch[0]
+    assert lines[0]["blocks_per_cu"] == launch[1]
+    ctx.adot_step(h, q, z, wl.steps, t)
+    ctx.sync()
+    for a, b in zip(to_np(h, q, z, t), to_np(h0, q0, z0, t0)):
+        assert np.array_equal(a, b)
+
+    # a second context finds the cached choice without tuning
+    ctx2 = dsve.Context.from_workload(wl)
+    ctx2.set_launch(64, 1, 12)
+    ctx2.autotune(h, q, z, trial_steps=4, cache_path=cache)
+    assert ctx2.get_launch()[:2] == launch[:2]
+    for c in (ref_ctx, ctx, ctx2):
+        c.close()
+
+
+def test_graph_recaptured_for_new_buffers(torch_dev, dsve):
+    wl = inputs.make_c2(n_cells=40_000, steps=120)
+    ctx = dsve.Context.from_workload(wl)
+    ctx.set_launch(256, 0, 60)
+    a = dsve.upload(wl)
+    b = dsve.upload(wl)
+    ctx.adot_step(*a[:3], 120, a[3])       # captures a graph for buffers a
+    ctx.adot_step(*b[:3], 60, b[3])        # different buffers: a new graph
+    ctx.adot_step(*b[:3], 60, b[3])        # reuses it
+    ctx.sync()
+    for x, y in zip(to_np(*a), to_np(*b)):
+        assert np.array_equal(x, y)
+    ref = oracle_run(wl, steps=120)
+    assert max_rel_l1(to_np(*a), ref) <= 1e-12
+    ctx.close()
+
+
+def test_non_default_stream(torch_dev, dsve):
+    torch = torch_dev
+    wl = inputs.make_c1()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = dsve.Context.from_workload(wl, stream=s)
+        h, q, z, t = dsve.upload(wl)
+        ctx.adot_step(h, q, z, wl.steps, t)
+        ctx.sync()
+    ref = oracle_run(wl)
+    assert max_rel_l1(to_np(h, q, z), ref) <= 1e-12
+    ctx.close()
+
+
+def test_cfl_reduce_mixed(torch_dev, dsve):
+    torch = torch_dev
+    wl = inputs.make_c3(n_cells=100_003)
+    ctx = dsve.Context.from_workload(wl, precision="mixed")
+    h, q, z, _ = dsve.upload(wl)
+    amax = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros_like(amax)
+    ctx.cfl_reduce(h, q, z, amax, dt)
+    ctx.sync()
+    ref = oracle.cfl_amax(wl.h, wl.q, wl.z, 9.81, 1.0 / (1 - wl.porosity[0]), wl.Ag[0])
+    assert abs(float(amax[0]) - ref) <= 1e-6 * ref
+    ctx.close()
+
+
+def _sampled_channels_check(dsve, wl, precision, tol, every):
+    ctx = dsve.Context.from_workload(wl, precision=precision)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, wl.steps, t)
+    ctx.sync()
+    got = to_np(h, q, z, t)
+    ctx.close()
+    chans = np.arange(0, wl.n_channels, every)
+    sub = wl.subset(chans)
+    ref = oracle_run(sub)
+    lo = wl.offsets[chans]
+    hi = wl.offsets[chans + 1]
+    sel = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+    got_sub = tuple(g[sel] for g in got[:3])
+    per = per_channel_rel_l1(got_sub, ref, sub.offsets)
+    assert per.max() <= tol, (per.max(), chans[per.argmax()])
+    np.testing.assert_allclose(got[3][chans], ref[3], rtol=1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_full_size_c4_fp64_sampled_channels(torch_dev, dsve):
+    # all 4096 channels (4.8e7 cells) for the full 500 steps; 16 channels checked
+    wl = inputs.make_c4()
+    _sampled_channels_check(dsve, wl, "fp64", 1e-12, every=256)
+
+
+def test_full_size_c5_mixed_sampled_channels(torch_dev, dsve):
+    # all 65536 channels (1.5e8 cells) for 300 of the 5000 steps; 32 channels checked
+    wl = inputs.make_c5()
+    wl.steps = 300
+    _sampled_channels_check(dsve, wl, "mixed", 1e-5, every=2048)
