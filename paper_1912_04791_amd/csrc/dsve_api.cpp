@@ -43,6 +43,7 @@ struct dsve_ctx {
     ChanInfo *d_ch = nullptr;
     int64_t *d_off = nullptr, *d_eoff = nullptr;
     GaussRule rule{};
+    double h_dx0 = 1.0;   // dx of channel 0 (the cell_update entry point divides by it)
 
     double *pp_h = nullptr, *pp_q = nullptr, *pp_z = nullptr;   // ping-pong copy
     unsigned long long *d_amax = nullptr;                        // [3][C]
@@ -234,8 +235,10 @@ static ChanInfo make_chan(int64_t cell0, int64_t n, double Ag, double por, doubl
     ci.ncell = n;
     const double xi = 1.0 / (1.0 - por);
     ci.kqg = 3.0 * xi * Ag * g;
+    ci.K1 = 1.0 + 3.0 * ci.kqg;
+    ci.K2 = 2.0 + 9.0 * ci.kqg;
     ci.cfl_dx = cfl * dx;
-    ci.dx = dx;
+    ci.inv_dx = 1.0 / dx;
     ci.q_in = q_in;
     ci.bcl = bcl;
     ci.bcr = bcr;
@@ -267,6 +270,7 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
     c->h_off = {0, n_cells};
     c->h_ch.push_back(make_chan(0, n_cells, p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right,
                                 p->q_in, p->cfl, p->g));
+    c->h_dx0 = p->dx;
     st = setup(c, hip_stream);
     if (st != DSVE_OK) {
         release(c);
@@ -350,7 +354,7 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
     FluctArgs a{};
     a.hL = hL; a.qL = qL; a.zL = zL; a.hR = hR; a.qR = qR; a.zR = zR;
     a.Dm = Dm; a.Dp = Dp; a.flags = ctx->d_flags; a.n = n;
-    a.g = ctx->g; a.kqg = ctx->h_ch[0].kqg; a.rule = ctx->rule;
+    a.g = ctx->g; a.ci = ctx->h_ch[0]; a.rule = ctx->rule;
     HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->stream));
     return DSVE_OK;
 }
@@ -362,7 +366,7 @@ dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const
     if (ctx->sticky != DSVE_OK) return ctx->sticky;
     if (ctx->batched) return fail(ctx, DSVE_E_ARG, "cell_update needs a single-channel context");
     if (!Dm || !Dp || !dt_dev || !h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
-    HIP_TRY(ctx, launch_cell_update(Dm, Dp, dt_dev, 0.0, ctx->h_ch[0].dx, ctx->n_cells, h, q, z,
+    HIP_TRY(ctx, launch_cell_update(Dm, Dp, dt_dev, 0.0, ctx->h_dx0, ctx->n_cells, h, q, z,
                                     ctx->stream));
     return DSVE_OK;
 }

@@ -3,8 +3,8 @@
 // Layout in HBM (all device memory):
 //   state      h[N], q[N], z[N] float64 SoA, channels back to back (caller's arrays
 //              plus one ping-pong copy owned by the context)
-//   ChanInfo   one 64-byte record per channel (offsets, closure constant, CFL constant,
-//              boundary conditions)
+//   ChanInfo   one 96-byte record per channel (offsets, closure constants, CFL constant,
+//              1/dx, boundary conditions)
 //   eoff       int64 [C+1]: first edge of each channel in the flat edge space;
 //              channel c has N_c + 1 edges, eoff[c] = off[c] + c, eoff[C] = total edges
 //   tile_chan  int32 per tile: channel of the tile's first edge
@@ -35,13 +35,14 @@ struct alignas(16) ChanInfo {
     int64_t cell0;   // first cell of the channel in the concatenated state
     int64_t ncell;   // N_c
     double kqg;      // 3 xi A_g g: xi dq_s/dq = kqg Fr^2 for the Grass law
+    double K1, K2;   // 1 + 3 kqg, 2 + 9 kqg (k1 = 3 + K1 Fr^2, k2 = Fr (18 - K2 Fr^2))
     double cfl_dx;   // cfl * dx  (dt = cfl_dx / amax)
-    double dx;
+    double inv_dx;   // 1 / dx
     double q_in;     // inflow discharge for BC_INFLOW_Q
     int32_t bcl, bcr;
-    int32_t pad[2];
+    int32_t pad[6];
 };
-static_assert(sizeof(ChanInfo) == 64, "ChanInfo must stay 64 bytes");
+static_assert(sizeof(ChanInfo) == 96, "ChanInfo layout changed");
 
 struct GaussRule {
     double s[kMaxGauss];
@@ -82,7 +83,8 @@ struct FluctArgs {
     double *Dm, *Dp;             // [3][n]
     unsigned int *flags;
     int64_t n;
-    double g, kqg;
+    double g;
+    ChanInfo ci;   // closure constants of the context (channel 0)
     GaussRule rule;
 };
 

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE
         if (have_edge)
             while (ge >= A.eoff[c + 1]) ++c;
         const ChanInfo ci = A.ch[c];
-        const Closure K = closure_of(ci.kqg);
+        const Closure K = closure_of(ci);
         const int64_t e = ge - A.eoff[c];
         bool bad = false;
         double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE
         unsigned long long sp_bits = 0ull;
         if (upd) {
             const double amax = __longlong_as_double((long long)A.amax_cur[c]);
-            const double dt = ci.cfl_dx / amax;
-            const double r = dt / ci.dx;
+            const double dt = ci.cfl_dx * rcp_h(amax);
+            const double r = dt * ci.inv_dx;
             const int64_t i = ci.cell0 + e;
             // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2})   (Sec. 3, Eq. scheme)
             const double hn = hR - r * (s_dm[t + 1] + Dp[0]);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
         bool bad = false;
         if (active) {
             while (i >= A.off[c + 1]) ++c;
-            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, closure_of(A.ch[c].kqg), bad));
+            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, closure_of(A.ch[c]), bad));
             bits = (unsigned long long)__double_as_longlong(sp);
         }
         raise_flag(A.flags, bad);
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
     bool bad = false;
     if (e < A.n) {
         double Dm[3], Dp[3];
-        edge_fluct<G, PREC>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.kqg), A.rule,
+        edge_fluct<G, PREC>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci), A.rule,
                             Dm, Dp, bad);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {

@@ -61,15 +61,6 @@ constexpr float kMixedFp64Band = 1e-3f;       // mixed form: 1 - |x| below this 
 #define DSVE_PRAGMA(x) _Pragma(#x)
 #define DSVE_UNROLL(n) DSVE_PRAGMA(unroll n)
 
-// Clamp to [-1, 1] keeping NaN (a NaN argument must stay visible downstream).
-__device__ __forceinline__ double clamp_unit(double x)
-{
-    return (x > 1.0) ? 1.0 : ((x < -1.0) ? -1.0 : x);
-}
-__device__ __forceinline__ float clamp_unitf(float x)
-{
-    return (x > 1.0f) ? 1.0f : ((x < -1.0f) ? -1.0f : x);
-}
 
 // 1/x: r (1 + e + e^2), e = 1 - x r
 __device__ __forceinline__ double rcp_h(double x)
@@ -105,7 +96,7 @@ __device__ __forceinline__ void trisect_correct(double x, double y, double &c, d
 __device__ __forceinline__ void trisect(double x, double &c, double &s)
 {
     const double v = fma(-x, x, 1.0);
-    const double y = (v > 0.0) ? v * rsqrt_h(v) : (v == 0.0 ? 0.0 : v);   // sin(phi)
+    const double y = v * rsqrt_h(fmax(v, 1e-300));   // sin(phi); 0 at x = +-1, NaN stays NaN
     const float th0 = acosf((float)x) * (1.0f / 3.0f);
     const double c0 = (double)__cosf(th0), s0 = (double)__sinf(th0);
     // renormalise: 1/sqrt(c0^2 + s0^2) to second order in e = c0^2 + s0^2 - 1 (|e| ~ 1e-7)
@@ -122,9 +113,9 @@ __device__ __forceinline__ void trisect(double x, double &c, double &s)
 struct Closure {
     double kqg, K1, K2;
 };
-__device__ __forceinline__ Closure closure_of(double kqg)
+__device__ __forceinline__ Closure closure_of(const ChanInfo &ci)
 {
-    return Closure{kqg, fma(3.0, kqg, 1.0), fma(9.0, kqg, 2.0)};
+    return Closure{ci.kqg, ci.K1, ci.K2};
 }
 
 // FP64 non-dimensional eigenstructure at one state.
@@ -146,8 +137,10 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     const double k2 = Fr * fma(-Fr2, K.K2, 18.0);
     const double r1 = rsqrt_h(k1);
     double x = (0.5 * k2) * (r1 * r1 * r1);   // k2 / sqrt(4 k1^3)
-    bad |= isfinite(k1) && isfinite(k2) && (!(k1 > 0.0) || fabs(x) > 1.0 + kAcosTol);
-    x = clamp_unit(x);
+    // complex roots: arccos argument beyond 1 + tol or k1 <= 0 (NaN compares false: a NaN
+    // state is reported as non-finite by the CFL maximum instead)
+    bad |= (fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0);
+    x = fmin(fmax(x, -1.0), 1.0);   // a NaN x only arises with a NaN Fr, which the roots carry
     double cs, sn;
     trisect(x, cs, sn);
     const double m = (2.0 / 3.0) * (k1 * r1);
