@@ -30,6 +30,13 @@ E_NONHYPERBOLIC = -4
 BC_TRANSMISSIVE = 0
 BC_PERIODIC = 1
 BC_INFLOW_Q = 2
+BC_FIXED_DEPTH = 3
+
+LAW_GRASS = 0       # q_s = A_g u^3                                   (Sec. 2, Eq. Grass)
+LAW_GRASS_THR = 1   # q_s = A_g (u - u_cr)^3, par = (u_cr,)           (Sec. 2, Eq. GrassThr)
+LAW_POWER = 2       # q_s = A_g u^beta, par = (beta,)                 (Sec. 5.1)
+LAW_MPM = 3         # Meyer-Peter & Mueller, par = (d50, S_g)         (Sec. 2, Eqs. MPM, Shields)
+LAW_VANRIJN = 4     # Van Rijn, par = (d50, S_g, nu, theta_cr)        (Sec. 2, Eqs. vanRijn, u_star)
 
 _CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99",
            "-Wall", "-Wextra", "-pthread"]
@@ -57,11 +64,23 @@ class Channel(ctypes.Structure):
         ("bc_left", ctypes.c_int),
         ("bc_right", ctypes.c_int),
         ("q_in", ctypes.c_double),
+        ("h_out", ctypes.c_double),
+        ("law", ctypes.c_int),
+        ("par", ctypes.c_double * 4),
+        ("ks", ctypes.c_double),
     ]
 
 
-class _Phys(ctypes.Structure):
-    _fields_ = [("g", ctypes.c_double), ("xi", ctypes.c_double), ("Ag", ctypes.c_double)]
+class Phys(ctypes.Structure):
+    """Physical parameters (mirrors ``or_phys``): g, xi, A_g, closure law and its parameters,
+    Strickler coefficient of the friction slope (0 = no friction)."""
+    _fields_ = [("g", ctypes.c_double), ("xi", ctypes.c_double), ("Ag", ctypes.c_double),
+                ("law", ctypes.c_int), ("par", ctypes.c_double * 4), ("ks", ctypes.c_double)]
+
+
+def make_phys(g: float, xi: float, Ag: float, law: int = LAW_GRASS, par=(), ks: float = 0.0) -> Phys:
+    pr = list(par) + [0.0] * (4 - len(par))
+    return Phys(g, xi, Ag, law, (ctypes.c_double * 4)(*pr), ks)
 
 
 _lib = None
@@ -78,22 +97,21 @@ def _load(lib_path: str | None = None):
         build(force=True)
     lib = ctypes.CDLL(path)
     lib.or_gauss.argtypes = [ctypes.c_int, _dp, _dp]
-    lib.or_eig_batch.argtypes = [_i64, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
-    lib.or_fluct_batch.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
+    _pp = ctypes.POINTER(Phys)
+    lib.or_eig_batch.argtypes = [_i64, _dp, _dp, _dp, _pp, _dp, _dp, _dp, _dp, _dp]
+    lib.or_fluct_batch.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp, _pp, ctypes.c_int, _dp, _dp,
                                    ctypes.c_int]
-    lib.or_cfl_amax.argtypes = [_i64, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, _dp, ctypes.c_int]
-    lib.or_step.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
-                            ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                            _dp, _dp, _dp, ctypes.c_int]
+    lib.or_cfl_amax.argtypes = [_i64, _dp, _dp, _dp, _pp, _dp, ctypes.c_int]
+    lib.or_step.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _pp, ctypes.c_int, ctypes.c_double,
+                            ctypes.c_double, _dp, _dp, _dp, ctypes.c_int]
     lib.or_run.argtypes = [ctypes.POINTER(Channel), _dp, _dp, _dp, ctypes.c_int, _dp, _dp,
                            ctypes.c_int]
     lib.or_run_batched.argtypes = [_i64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Channel),
                                    _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int]
     lib.or_channel_size.restype = ctypes.c_int
+    lib.or_phys_size.restype = ctypes.c_int
     assert lib.or_channel_size() == ctypes.sizeof(Channel), "or_channel layout mismatch"
+    assert lib.or_phys_size() == ctypes.sizeof(Phys), "or_phys layout mismatch"
     if lib_path is None:
         _lib = lib
     return lib
@@ -130,7 +148,8 @@ def gauss(G: int, lib=None):
     return s, w
 
 
-def eigensystem(h, q, z, g: float, xi: float, Ag: float, lib=None, check: bool = True):
+def eigensystem(h, q, z, g: float, xi: float, Ag: float, lib=None, check: bool = True,
+                law: int = LAW_GRASS, par=(), ks: float = 0.0):
     """Closed-form eigenstructure at each state (Sec. 3.3 steps 1-5).
 
     Returns dict with ``lam`` [n,3] (lambda_1 <= lambda_2 <= lambda_3), ``R`` [n,3,3]
@@ -145,15 +164,16 @@ def eigensystem(h, q, z, g: float, xi: float, Ag: float, lib=None, check: bool =
     Rinv = np.zeros((n, 3, 3))
     A = np.zeros((n, 3, 3))
     absA = np.zeros((n, 3, 3))
-    st = lib.or_eig_batch(n, _ptr(h), _ptr(q), _ptr(z), g, xi, Ag, _ptr(lam), _ptr(R), _ptr(Rinv),
-                          _ptr(A), _ptr(absA))
+    ph = make_phys(g, xi, Ag, law, par, ks)
+    st = lib.or_eig_batch(n, _ptr(h), _ptr(q), _ptr(z), ctypes.byref(ph), _ptr(lam), _ptr(R),
+                          _ptr(Rinv), _ptr(A), _ptr(absA))
     if check and st != OK:
         raise OracleError(st, "eigensystem")
     return {"lam": lam, "R": R, "Rinv": Rinv, "A": A, "absA": absA, "status": st}
 
 
 def fluct(WL, WR, g: float, xi: float, Ag: float, G: int = 3, nthreads: int | None = None,
-          lib=None, check: bool = True):
+          lib=None, check: bool = True, law: int = LAW_GRASS, par=(), ks: float = 0.0):
     """DOT fluctuations for n independent edges (Sec. 3.1, Eq. DOTjumpN).
 
     ``WL``/``WR`` are (h, q, z) tuples of length-n arrays (left / right states).
@@ -165,19 +185,22 @@ def fluct(WL, WR, g: float, xi: float, Ag: float, G: int = 3, nthreads: int | No
     n = hL.size
     Dm = np.zeros((3, n))
     Dp = np.zeros((3, n))
-    st = lib.or_fluct_batch(n, _ptr(hL), _ptr(qL), _ptr(zL), _ptr(hR), _ptr(qR), _ptr(zR), g, xi, Ag,
-                            G, _ptr(Dm), _ptr(Dp), nthreads or default_threads())
+    ph = make_phys(g, xi, Ag, law, par, ks)
+    st = lib.or_fluct_batch(n, _ptr(hL), _ptr(qL), _ptr(zL), _ptr(hR), _ptr(qR), _ptr(zR),
+                            ctypes.byref(ph), G, _ptr(Dm), _ptr(Dp), nthreads or default_threads())
     if check and st != OK:
         raise OracleError(st, "fluct")
     return Dm, Dp
 
 
-def cfl_amax(h, q, z, g: float, xi: float, Ag: float, nthreads: int | None = None, lib=None):
+def cfl_amax(h, q, z, g: float, xi: float, Ag: float, nthreads: int | None = None, lib=None,
+             law: int = LAW_GRASS, par=(), ks: float = 0.0):
     """max over cells of max_m |lambda_m(W_i)| (the CFL reduction)."""
     lib = lib or _load()
     h, q, z = _f64(h).ravel(), _f64(q).ravel(), _f64(z).ravel()
     out = ctypes.c_double(0.0)
-    st = lib.or_cfl_amax(h.size, _ptr(h), _ptr(q), _ptr(z), g, xi, Ag, ctypes.byref(out),
+    ph = make_phys(g, xi, Ag, law, par, ks)
+    st = lib.or_cfl_amax(h.size, _ptr(h), _ptr(q), _ptr(z), ctypes.byref(ph), ctypes.byref(out),
                          nthreads or default_threads())
     if st != OK:
         raise OracleError(st, "cfl_amax")
@@ -185,14 +208,16 @@ def cfl_amax(h, q, z, g: float, xi: float, Ag: float, nthreads: int | None = Non
 
 
 def step(h, q, z, ghost_l, ghost_r, g: float, xi: float, Ag: float, G: int, dt: float, dx: float,
-         nthreads: int | None = None, lib=None):
-    """One path-conservative update (Sec. 3, Eq. scheme, S = 0) with given ghosts and dt."""
+         nthreads: int | None = None, lib=None, law: int = LAW_GRASS, par=(), ks: float = 0.0):
+    """One path-conservative update (Sec. 3, Eq. scheme; friction point source if ks > 0)
+    with given ghosts and dt."""
     lib = lib or _load()
     h, q, z = _f64(h).ravel(), _f64(q).ravel(), _f64(z).ravel()
     gl, gr = _f64(ghost_l), _f64(ghost_r)
     hn, qn, zn = np.zeros_like(h), np.zeros_like(q), np.zeros_like(z)
-    st = lib.or_step(h.size, _ptr(h), _ptr(q), _ptr(z), _ptr(gl), _ptr(gr), g, xi, Ag, G, dt, dx,
-                     _ptr(hn), _ptr(qn), _ptr(zn), nthreads or default_threads())
+    ph = make_phys(g, xi, Ag, law, par, ks)
+    st = lib.or_step(h.size, _ptr(h), _ptr(q), _ptr(z), _ptr(gl), _ptr(gr), ctypes.byref(ph), G, dt,
+                     dx, _ptr(hn), _ptr(qn), _ptr(zn), nthreads or default_threads())
     if st != OK:
         raise OracleError(st, "step")
     return hn, qn, zn
@@ -211,10 +236,16 @@ class ChannelSpec:
     bc_left: int = BC_TRANSMISSIVE
     bc_right: int = BC_TRANSMISSIVE
     q_in: float = 0.0
+    h_out: float = 0.0
+    law: int = LAW_GRASS
+    par: tuple = ()
+    ks: float = 0.0
 
     def to_c(self) -> Channel:
+        pr = list(self.par) + [0.0] * (4 - len(self.par))
         return Channel(self.n_cells, self.g, 1.0 / (1.0 - self.porosity), self.Ag, self.n_gauss,
-                       self.cfl, self.dx, self.bc_left, self.bc_right, self.q_in)
+                       self.cfl, self.dx, self.bc_left, self.bc_right, self.q_in, self.h_out,
+                       self.law, (ctypes.c_double * 4)(*pr), self.ks)
 
 
 def run(spec: ChannelSpec, h, q, z, n_steps: int, t0: float = 0.0, nthreads: int | None = None,

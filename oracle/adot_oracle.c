@@ -10,14 +10,18 @@
  * implementation of the DOT Riemann solver for the de Saint Venant-Exner
  * morphodynamic model"):
  *   - the flux matrix A(W) of the quasi-linear dSVE system   (Sec. 2, Eq. W&A_definition)
- *   - the Grass bed-load closure and its derivatives          (Sec. 2 Eq. Grass; Sec. 3.3 step 1)
+ *   - bed-load closures and their derivatives: Grass (Eq. Grass), Grass with a threshold
+ *     (Eq. GrassThr), the power law of Sec. 5.1, Meyer-Peter & Mueller (Eqs. MPM, Shields),
+ *     Van Rijn (Eqs. vanRijn, u_star)                         (Sec. 2; Sec. 3.3 step 1)
+ *   - the Strickler friction slope and its point source       (Sec. 2; Sec. 3, Eq. scheme)
  *   - the closed-form eigenvalues (trigonometric Cardano)     (Sec. 3.3, Eqs. charPol, lambda,
  *                                                              parameters, parameters_bis)
  *   - right / left eigenvectors                               (Sec. 3.3, Eqs. RR, RR-1, circPerm)
  *   - |A| = R |Lambda| R^-1 as an explicit triple product     (Sec. 3.1 Eq. asbA; Sec. 3.3 Eq. ExAbsA)
  *   - the DOT fluctuations by G-point Gauss quadrature along
  *     the segment path                                        (Sec. 3.1, Eqs. path, DOTjump, DOTjumpN)
- *   - the first-order path-conservative cell update, S = 0    (Sec. 3, Eq. scheme; Sec. 4 friction neglected)
+ *   - the first-order path-conservative cell update, with the friction source as a
+ *     point source (S = 0 when no Strickler coefficient is given, as in Sec. 4) (Sec. 3, Eq. scheme)
  *   - the CFL time step  dt = CFL dx / max_i max_m |lambda_m(W_i)|  (reading: the paper names
  *     the CFL condition but does not print the rule)
  *
@@ -40,6 +44,13 @@
 #define OR_BC_TRANSMISSIVE 0
 #define OR_BC_PERIODIC 1
 #define OR_BC_INFLOW_Q 2
+#define OR_BC_FIXED_DEPTH 3
+
+#define OR_LAW_GRASS 0
+#define OR_LAW_GRASS_THR 1
+#define OR_LAW_POWER 2
+#define OR_LAW_MPM 3
+#define OR_LAW_VANRIJN 4
 
 /* Tolerance on the arccos argument before it is declared outside [-1, 1]
  * (reading: rounding may push a real-root argument marginally past 1). */
@@ -47,11 +58,23 @@
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
-/* Physical parameters of one channel. */
+/* Physical parameters of one channel.
+ *   law  OR_LAW_*; par[] depends on it:
+ *        GRASS      q_s = A_g u^3                               (no par)
+ *        GRASS_THR  q_s = A_g (u - u_cr)^3                      par[0] = u_cr
+ *        POWER      q_s = A_g u^beta  (A_g is the coefficient)  par[0] = beta
+ *        MPM        Meyer-Peter & Mueller                       par[0] = d50, par[1] = S_g
+ *        VANRIJN    Van Rijn                                    par[0] = d50, par[1] = S_g,
+ *                                                               par[2] = nu, par[3] = theta_cr
+ *   ks   Strickler coefficient K_s of the friction slope (0: no friction; MPM and Van Rijn
+ *        need it, their Shields stress and shear velocity come from s_f). */
 typedef struct {
     double g;  /* gravitational acceleration */
     double xi; /* 1 / (1 - porosity), Sec. 2 */
-    double Ag; /* Grass coefficient A_g, Eq. Grass */
+    double Ag; /* coefficient of the Grass-type laws */
+    int law;
+    double par[4];
+    double ks;
 } or_phys;
 
 /* One channel of the scheme. */
@@ -61,7 +84,11 @@ typedef struct {
     int n_gauss;
     double cfl, dx;
     int bc_left, bc_right;
-    double q_in; /* discharge imposed by an inflow-q boundary */
+    double q_in;  /* discharge imposed by an inflow-q boundary */
+    double h_out; /* depth imposed by a fixed-depth boundary */
+    int law;
+    double par[4];
+    double ks;
 } or_channel;
 
 /* ------------------------------------------------------------------------- */
@@ -122,6 +149,90 @@ static void grass_derivatives(double h, double q, double Ag, double *dqs_dh, dou
     *dqs_dq = 3.0 * Ag * u * u / h;
 }
 
+static double sign_of(double v) { return (v > 0.0) ? 1.0 : ((v < 0.0) ? -1.0 : 0.0); }
+
+/* A law of the velocity only, q_s = f(u) with u = q/h: by the chain rule
+ * dq_s/dq = f'(u) / h and dq_s/dh = -f'(u) u / h. */
+static void velocity_law(double h, double q, double dfdu, double *dqs_dh, double *dqs_dq)
+{
+    double u = q / h;
+    *dqs_dq = dfdu / h;
+    *dqs_dh = -dfdu * u / h;
+}
+
+/* Step 1 for every closure of Sec. 2 (and the power law of Sec. 5.1).
+ * Readings: the laws act in the direction of the flow (odd in u or q); Grass with a
+ * threshold transports only when |u| > u_cr, q_s = A_g sign(u) (|u| - u_cr)^3; the power
+ * law is q_s = A_g sign(u) |u|^beta; in the Shields stress and the shear velocity the
+ * friction slope enters through its magnitude s_f = q^2 / (K_s^2 h^(10/3)) (Sec. 2);
+ * Van Rijn takes the dimensionless grain size D_* = d50 (g (S_g - 1) / nu^2)^(1/3) and the
+ * critical shear velocity from u_*cr^2 = theta_cr g (S_g - 1) d50 (the printed forms are
+ * not dimensionless / not the Shields relation). */
+static void qs_derivatives(double h, double q, const or_phys *p, double *dqs_dh, double *dqs_dq)
+{
+    switch (p->law) {
+    case OR_LAW_GRASS:
+        grass_derivatives(h, q, p->Ag, dqs_dh, dqs_dq);
+        return;
+    case OR_LAW_GRASS_THR: {
+        double u = q / h;
+        double ex = fabs(u) - p->par[0];
+        double dfdu = (ex > 0.0) ? 3.0 * p->Ag * ex * ex : 0.0;
+        velocity_law(h, q, dfdu, dqs_dh, dqs_dq);
+        return;
+    }
+    case OR_LAW_POWER: {
+        double u = q / h;
+        double beta = p->par[0];
+        double dfdu = (u != 0.0) ? p->Ag * beta * pow(fabs(u), beta - 1.0) : 0.0;
+        velocity_law(h, q, dfdu, dqs_dh, dqs_dq);
+        return;
+    }
+    case OR_LAW_MPM: {
+        /* q_s = Phi(theta) sqrt(g (S_g-1) d50^3), Phi = 8 (theta - 0.047)^(3/2) above 0.047,
+         * theta = s_f h / ((S_g - 1) d50)  (Eqs. MPM, Shields) */
+        double d50 = p->par[0], Sg = p->par[1];
+        double sf = q * q / (p->ks * p->ks * pow(h, 10.0 / 3.0));
+        double theta = sf * h / ((Sg - 1.0) * d50);
+        if (!(theta > 0.047)) { *dqs_dh = 0.0; *dqs_dq = 0.0; return; }
+        double scale = sqrt(p->g * (Sg - 1.0) * d50 * d50 * d50);
+        double dqs_dtheta = scale * 12.0 * sqrt(theta - 0.047);   /* d/dtheta of 8 (theta - 0.047)^(3/2) */
+        /* theta = q^2 / (K_s^2 (S_g-1) d50 h^(7/3)): dtheta/dq = 2 theta / q, dtheta/dh = -(7/3) theta / h */
+        *dqs_dq = dqs_dtheta * 2.0 * theta / fabs(q);
+        *dqs_dh = sign_of(q) * dqs_dtheta * (-7.0 / 3.0) * theta / h;
+        return;
+    }
+    case OR_LAW_VANRIJN: {
+        /* q_s = 0.053 T^2.1 / D_*^0.3 sqrt(g (S_g-1) d50^3), T = (u_*^2 - u_*cr^2) / u_*cr^2,
+         * u_*^2 = g h s_f  (Eqs. vanRijn, u_star) */
+        double d50 = p->par[0], Sg = p->par[1], nu = p->par[2], theta_cr = p->par[3];
+        double sf = q * q / (p->ks * p->ks * pow(h, 10.0 / 3.0));
+        double us2 = p->g * h * sf;
+        double uscr2 = theta_cr * p->g * (Sg - 1.0) * d50;
+        double T = (us2 - uscr2) / uscr2;
+        if (!(T > 0.0)) { *dqs_dh = 0.0; *dqs_dq = 0.0; return; }
+        double Dstar = d50 * cbrt(p->g * (Sg - 1.0) / (nu * nu));
+        double scale = 0.053 / pow(Dstar, 0.3) * sqrt(p->g * (Sg - 1.0) * d50 * d50 * d50);
+        double dqs_dT = scale * 2.1 * pow(T, 1.1);
+        /* u_*^2 = g q^2 / (K_s^2 h^(7/3)): dT/dq = 2 (T + 1) / q, dT/dh = -(7/3) (T + 1) / h */
+        *dqs_dq = dqs_dT * 2.0 * (T + 1.0) / fabs(q);
+        *dqs_dh = sign_of(q) * dqs_dT * (-7.0 / 3.0) * (T + 1.0) / h;
+        return;
+    }
+    default:
+        *dqs_dh = NAN;
+        *dqs_dq = NAN;
+        return;
+    }
+}
+
+/* Friction slope (Sec. 2) with the sign of the flow, s_f = q |q| / (K_s^2 h^(10/3)), so that
+ * the momentum source -c^2 s_f opposes the flow (reading: the printed q^2 is the magnitude). */
+static double friction_slope(double h, double q, double ks)
+{
+    return q * fabs(q) / (ks * ks * pow(h, 10.0 / 3.0));
+}
+
 /* Flux matrix of the quasi-linear system (Sec. 2, Eq. W&A_definition):
  *   A = [[0, 1, 0], [c^2 - u^2, 2u, c^2], [xi dq_s/dh, xi dq_s/dq, 0]],
  * u = q/h, c = sqrt(g h).  Row-major 3x3. */
@@ -131,7 +242,7 @@ void or_flux_matrix(const double W[3], const or_phys *p, double A[9])
     double u = q / h;
     double c2 = p->g * h;
     double dqs_dh, dqs_dq;
-    grass_derivatives(h, q, p->Ag, &dqs_dh, &dqs_dq);
+    qs_derivatives(h, q, p, &dqs_dh, &dqs_dq);
     A[0] = 0.0;              A[1] = 1.0;               A[2] = 0.0;
     A[3] = c2 - u * u;       A[4] = 2.0 * u;           A[5] = c2;
     A[6] = p->xi * dqs_dh;   A[7] = p->xi * dqs_dq;    A[8] = 0.0;
@@ -165,7 +276,7 @@ int or_eigensystem(const double W[3], const or_phys *p, double lam[3], double R[
     double Fr = u / c;
     /* step 1 */
     double dqs_dh, dqs_dq;
-    grass_derivatives(h, q, p->Ag, &dqs_dh, &dqs_dq);
+    qs_derivatives(h, q, p, &dqs_dh, &dqs_dq);
     /* step 2 */
     double k1 = 3.0 + Fr * Fr + 3.0 * p->xi * dqs_dq;
     double k2 = -2.0 * Fr * Fr * Fr + 18.0 * Fr * (1.0 + p->xi * dqs_dq) + 27.0 * p->xi * dqs_dh / c;
@@ -312,10 +423,10 @@ static void parallel_for(int64_t n, int nthreads, range_fn fn, void *ctx)
  * Outputs (any may be NULL): lam[3n] (lam[3i+m]), R[9n], Rinv[9n], A[9n], absA[9n]
  * (each 3x3 row-major per state). Returns OR_E_NONHYPERBOLIC if any state's
  * arccos argument was out of range. */
-int or_eig_batch(int64_t n, const double *h, const double *q, const double *z, double g, double xi,
-                 double Ag, double *lam, double *R, double *Rinv, double *A, double *absA)
+int or_eig_batch(int64_t n, const double *h, const double *q, const double *z, const or_phys *pp,
+                 double *lam, double *R, double *Rinv, double *A, double *absA)
 {
-    or_phys p = {g, xi, Ag};
+    or_phys p = *pp;
     int nonhyp = 0;
     for (int64_t i = 0; i < n; ++i) {
         double W[3] = {h[i], q[i], z[i]};
@@ -358,7 +469,7 @@ static void fluct_batch_range(void *vctx, int64_t lo, int64_t hi, int part)
 }
 
 int or_fluct_batch(int64_t n, const double *hL, const double *qL, const double *zL, const double *hR,
-                   const double *qR, const double *zR, double g, double xi, double Ag, int G, double *Dm,
+                   const double *qR, const double *zR, const or_phys *pp, int G, double *Dm,
                    double *Dp, int nthreads)
 {
     if (n < 0 || G < 1 || G > 64) return OR_E_ARG;
@@ -366,7 +477,7 @@ int or_fluct_batch(int64_t n, const double *hL, const double *qL, const double *
     or_gauss(G, s, w);
     fluct_batch_ctx *c = (fluct_batch_ctx *)calloc(1, sizeof(fluct_batch_ctx));
     c->hL = hL; c->qL = qL; c->zL = zL; c->hR = hR; c->qR = qR; c->zR = zR;
-    c->p.g = g; c->p.xi = xi; c->p.Ag = Ag;
+    c->p = *pp;
     c->G = G; c->s = s; c->w = w; c->n = n; c->Dm = Dm; c->Dp = Dp;
     parallel_for(n, nthreads, fluct_batch_range, c);
     int nonhyp = 0;
@@ -415,10 +526,10 @@ static double amax_of(int64_t n, const double *h, const double *q, const double 
     return m;
 }
 
-int or_cfl_amax(int64_t n, const double *h, const double *q, const double *z, double g, double xi,
-                double Ag, double *amax, int nthreads)
+int or_cfl_amax(int64_t n, const double *h, const double *q, const double *z, const or_phys *pp,
+                double *amax, int nthreads)
 {
-    or_phys p = {g, xi, Ag};
+    or_phys p = *pp;
     int nonhyp = 0;
     *amax = amax_of(n, h, q, z, &p, nthreads, &nonhyp);
     if (nonhyp) return OR_E_NONHYPERBOLIC;
@@ -474,11 +585,14 @@ static void update_range(void *vctx, int64_t lo, int64_t hi, int part)
         c->hn[i] = c->h[i] - r * (c->Dm[0 * E + i + 1] + c->Dp[0 * E + i]);
         c->qn[i] = c->q[i] - r * (c->Dm[1 * E + i + 1] + c->Dp[1 * E + i]);
         c->zn[i] = c->z[i] - r * (c->Dm[2 * E + i + 1] + c->Dp[2 * E + i]);
+        /* point source dt S(W_i^n), S = (0, -c^2 s_f, 0) with c^2 = g h (Sec. 2, Eq. scheme) */
+        if (c->p.ks > 0.0)
+            c->qn[i] += c->dt * (-c->p.g * c->h[i] * friction_slope(c->h[i], c->q[i], c->p.ks));
     }
 }
 
 int or_step(int64_t N, const double *h, const double *q, const double *z, const double ghost_l[3],
-            const double ghost_r[3], double g, double xi, double Ag, int G, double dt, double dx,
+            const double ghost_r[3], const or_phys *pp, int G, double dt, double dx,
             double *hn, double *qn, double *zn, int nthreads)
 {
     if (N < 1 || G < 1 || G > 64) return OR_E_ARG;
@@ -486,7 +600,7 @@ int or_step(int64_t N, const double *h, const double *q, const double *z, const 
     or_gauss(G, s, w);
     step_ctx *c = (step_ctx *)calloc(1, sizeof(step_ctx));
     c->h = h; c->q = q; c->z = z; c->gl = ghost_l; c->gr = ghost_r; c->N = N;
-    c->p.g = g; c->p.xi = xi; c->p.Ag = Ag; c->G = G; c->s = s; c->w = w;
+    c->p = *pp; c->G = G; c->s = s; c->w = w;
     c->Dm = (double *)malloc(sizeof(double) * 3 * (N + 1));
     c->Dp = (double *)malloc(sizeof(double) * 3 * (N + 1));
     c->hn = hn; c->qn = qn; c->zn = zn; c->dt = dt; c->dx = dx;
@@ -502,7 +616,8 @@ int or_step(int64_t N, const double *h, const double *q, const double *z, const 
 
 /* Ghost states from the boundary conditions (reading: the paper does not spell
  * out the ghost-cell form):  transmissive = copy of the adjacent cell;
- * periodic = the cell at the other end; inflow-q = (h, q_in, z) of the adjacent cell. */
+ * periodic = the cell at the other end; inflow-q = (h, q_in, z) of the adjacent cell;
+ * fixed depth = (h_out, q, z) of the adjacent cell. */
 static void ghost_states(const or_channel *ch, const double *h, const double *q, const double *z,
                          double gl[3], double gr[3])
 {
@@ -510,11 +625,13 @@ static void ghost_states(const or_channel *ch, const double *h, const double *q,
     switch (ch->bc_left) {
     case OR_BC_PERIODIC: gl[0] = h[N - 1]; gl[1] = q[N - 1]; gl[2] = z[N - 1]; break;
     case OR_BC_INFLOW_Q: gl[0] = h[0]; gl[1] = ch->q_in; gl[2] = z[0]; break;
+    case OR_BC_FIXED_DEPTH: gl[0] = ch->h_out; gl[1] = q[0]; gl[2] = z[0]; break;
     default: gl[0] = h[0]; gl[1] = q[0]; gl[2] = z[0]; break;
     }
     switch (ch->bc_right) {
     case OR_BC_PERIODIC: gr[0] = h[0]; gr[1] = q[0]; gr[2] = z[0]; break;
     case OR_BC_INFLOW_Q: gr[0] = h[N - 1]; gr[1] = ch->q_in; gr[2] = z[N - 1]; break;
+    case OR_BC_FIXED_DEPTH: gr[0] = ch->h_out; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
     default: gr[0] = h[N - 1]; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
     }
 }
@@ -524,8 +641,10 @@ static int check_channel(const or_channel *ch)
     if (ch->n_cells < 1) return OR_E_ARG;
     if (ch->n_gauss < 1 || ch->n_gauss > 64) return OR_E_ARG;
     if (!(ch->cfl > 0.0) || !(ch->dx > 0.0) || !(ch->g > 0.0) || !(ch->xi >= 1.0)) return OR_E_ARG;
-    if (ch->bc_left < 0 || ch->bc_left > 2 || ch->bc_right < 0 || ch->bc_right > 2) return OR_E_ARG;
+    if (ch->bc_left < 0 || ch->bc_left > 3 || ch->bc_right < 0 || ch->bc_right > 3) return OR_E_ARG;
     if ((ch->bc_left == OR_BC_PERIODIC) != (ch->bc_right == OR_BC_PERIODIC)) return OR_E_ARG;
+    if (ch->law < OR_LAW_GRASS || ch->law > OR_LAW_VANRIJN) return OR_E_ARG;
+    if ((ch->law == OR_LAW_MPM || ch->law == OR_LAW_VANRIJN) && !(ch->ks > 0.0)) return OR_E_ARG;
     return OR_OK;
 }
 
@@ -539,7 +658,8 @@ int or_run(const or_channel *ch, double *h, double *q, double *z, int n_steps, d
     int st = check_channel(ch);
     if (st != OR_OK || n_steps < 0) return OR_E_ARG;
     int64_t N = ch->n_cells;
-    or_phys p = {ch->g, ch->xi, ch->Ag};
+    or_phys p = {ch->g, ch->xi, ch->Ag, ch->law, {ch->par[0], ch->par[1], ch->par[2], ch->par[3]},
+                 ch->ks};
     double *hn = (double *)malloc(sizeof(double) * N);
     double *qn = (double *)malloc(sizeof(double) * N);
     double *zn = (double *)malloc(sizeof(double) * N);
@@ -552,8 +672,7 @@ int or_run(const or_channel *ch, double *h, double *q, double *z, int n_steps, d
         if (nonhyp) { status = OR_E_NONHYPERBOLIC; break; }
         if (!isfinite(amax) || !(amax > 0.0)) { status = OR_E_NONFINITE; break; }
         double dt = ch->cfl * ch->dx / amax;
-        st = or_step(N, h, q, z, gl, gr, ch->g, ch->xi, ch->Ag, ch->n_gauss, dt, ch->dx, hn, qn, zn,
-                     nthreads);
+        st = or_step(N, h, q, z, gl, gr, &p, ch->n_gauss, dt, ch->dx, hn, qn, zn, nthreads);
         if (st != OR_OK) { status = st; break; }
         memcpy(h, hn, sizeof(double) * N);
         memcpy(q, qn, sizeof(double) * N);
@@ -609,5 +728,6 @@ int or_run_batched(int64_t n_channels, const int64_t *off, const or_channel *chs
     return status;
 }
 
-/* Size of the channel record, so the caller can check its own struct layout. */
+/* Sizes of the records, so the caller can check its own struct layouts. */
 int or_channel_size(void) { return (int)sizeof(or_channel); }
+int or_phys_size(void) { return (int)sizeof(or_phys); }

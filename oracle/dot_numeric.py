@@ -106,3 +106,93 @@ def run(h, q, z, n_steps, dx, g, xi, Ag, G=3, cfl=0.9, periodic=False):
         W = W - dt / dx * (Dm[:, 1:] + Dp[:, :-1])
         t += dt
     return W[0], W[1], W[2], t
+
+
+# ---------------------------------------------------------------------------
+# Closures of Sec. 2 (and the power law of Sec. 5.1) as functions q_s(h, q), written to accept
+# complex arguments so that complex-step differentiation gives dq_s/dh and dq_s/dq without
+# any hand-derived derivative.  The branch (threshold, direction) is taken on the real part.
+# Readings shared with the oracle: the laws act in the direction of the flow; Grass with a
+# threshold is A_g sign(u) (|u| - u_cr)^3 above the threshold; the friction slope enters the
+# Shields stress and the shear velocity as q^2 / (K_s^2 h^(10/3)); Van Rijn uses
+# D_* = d50 (g (S_g - 1) / nu^2)^(1/3) and u_*cr^2 = theta_cr g (S_g - 1) d50.
+LAW_GRASS, LAW_GRASS_THR, LAW_POWER, LAW_MPM, LAW_VANRIJN = 0, 1, 2, 3, 4
+
+
+def _sgn(v):
+    return np.sign(np.real(v))
+
+
+def qs_law(h, q, g, law, Ag=0.0, par=(), ks=0.0):
+    par = tuple(par) + (0.0,) * (4 - len(par))
+    u = q / h
+    if law == LAW_GRASS:
+        return Ag * u ** 3
+    if law == LAW_GRASS_THR:
+        s = _sgn(u)
+        ex = s * u - par[0]
+        return np.where(np.real(ex) > 0, Ag * s * ex ** 3, 0.0 * ex)
+    if law == LAW_POWER:
+        s = _sgn(u)
+        return Ag * s * (s * u) ** par[0]
+    d50, Sg = par[0], par[1]
+    sf = q * q / (ks * ks * h ** (10.0 / 3.0))
+    if law == LAW_MPM:
+        theta = sf * h / ((Sg - 1.0) * d50)
+        ex = theta - 0.047
+        return np.where(np.real(ex) > 0, _sgn(q) * 8.0 * ex ** 1.5, 0.0 * ex) * \
+            np.sqrt(g * (Sg - 1.0) * d50 ** 3)
+    if law == LAW_VANRIJN:
+        nu, theta_cr = par[2], par[3]
+        us2 = g * h * sf
+        uscr2 = theta_cr * g * (Sg - 1.0) * d50
+        T = (us2 - uscr2) / uscr2
+        Dstar = d50 * (g * (Sg - 1.0) / nu ** 2) ** (1.0 / 3.0)
+        return np.where(np.real(T) > 0, _sgn(q) * 0.053 * T ** 2.1, 0.0 * T) / Dstar ** 0.3 * \
+            np.sqrt(g * (Sg - 1.0) * d50 ** 3)
+    raise ValueError(law)
+
+
+def qs_derivatives_cs(h, q, g, law, Ag=0.0, par=(), ks=0.0, eps=1e-30):
+    """(dq_s/dh, dq_s/dq) by complex-step differentiation of qs_law."""
+    h = np.asarray(h, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    dh = np.imag(qs_law(h + 1j * eps, q + 0j, g, law, Ag, par, ks)) / eps
+    dq = np.imag(qs_law(h + 0j, q + 1j * eps, g, law, Ag, par, ks)) / eps
+    return dh, dq
+
+
+def flux_matrix_law(h, q, g, xi, law, Ag=0.0, par=(), ks=0.0):
+    """A(W) of Eq. W&A_definition with the closure's derivatives by complex step."""
+    h = np.asarray(h, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    u = q / h
+    c2 = g * h
+    dh, dq = qs_derivatives_cs(h, q, g, law, Ag, par, ks)
+    A = np.zeros(h.shape + (3, 3))
+    A[..., 0, 1] = 1.0
+    A[..., 1, 0] = c2 - u * u
+    A[..., 1, 1] = 2.0 * u
+    A[..., 1, 2] = c2
+    A[..., 2, 0] = xi * dh
+    A[..., 2, 1] = xi * dq
+    return A
+
+
+def fluct_law(WL, WR, g, xi, law, Ag=0.0, par=(), ks=0.0, G=3):
+    """Numerical-eigensolver DOT fluctuations for any closure -> ([3,n], [3,n])."""
+    WL = np.asarray(WL, dtype=np.float64)
+    WR = np.asarray(WR, dtype=np.float64)
+    dW = WR - WL
+    s, w = gauss01(G)
+    Sm = np.zeros_like(dW)
+    Sp = np.zeros_like(dW)
+    for k in range(G):
+        Psi = WL + s[k] * dW
+        A = flux_matrix_law(Psi[0], Psi[1], g, xi, law, Ag, par, ks)
+        aA = abs_matrix(A)
+        Adw = np.einsum("nij,jn->in", A, dW)
+        aAdw = np.einsum("nij,jn->in", aA, dW)
+        Sm += w[k] * (Adw - aAdw)
+        Sp += w[k] * (Adw + aAdw)
+    return 0.5 * Sm, 0.5 * Sp

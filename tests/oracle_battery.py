@@ -61,6 +61,48 @@ def checks(lib):
     out["fluct"] = bool(np.max(np.abs(Dm - rm)) <= 1e-11 * sc and
                         np.max(np.abs(Dp - rp)) <= 1e-11 * sc)
 
+    # other closures: third row of A against complex-step derivatives of q_s
+    laws = {"closure_grass_thr": (oracle.LAW_GRASS_THR, 0.0024, (0.3,), 0.0),
+            "closure_power": (oracle.LAW_POWER, 1.45e-3, (5.0,), 0.0),
+            "closure_mpm": (oracle.LAW_MPM, 0.0, (3.2e-4, 2.6), 20.0),
+            "closure_vanrijn": (oracle.LAW_VANRIJN, 0.0, (3.2e-4, 2.6, 1e-6, 0.03), 20.0)}
+    hh = rng.uniform(0.1, 0.8, 100)
+    uu = rng.uniform(0.8, 3.0, 100) * np.where(rng.uniform(size=100) < 0.5, -1.0, 1.0)
+    for name, (law, Ag, par, ks) in laws.items():
+        e2 = oracle.eigensystem(hh, hh * uu, 0 * hh, G, xi, Ag, lib=lib, check=False, law=law, par=par,
+                                ks=ks)
+        ref = dot_numeric.flux_matrix_law(hh, hh * uu, G, xi, law, Ag, par, ks)
+        out[name] = bool(np.max(np.abs(e2["A"][:, 2, :2] - ref[:, 2, :2]))
+                         <= 1e-10 * np.abs(ref[:, 2, :2]).max())
+
+    # friction: uniform flow down a slope whose friction slope equals the bed slope is steady
+    ksf, h0, q0, n, dxf = 40.0, 0.3, 0.45, 60, 0.05
+    s0 = q0 * q0 / (ksf * ksf * h0 ** (10.0 / 3.0))
+    zf = 1.0 - s0 * (np.arange(n) + 0.5) * dxf
+    spec = oracle.ChannelSpec(n_cells=n, dx=dxf, Ag=0.005, porosity=0.4, ks=ksf)
+    try:
+        h1, q1, z1, _ = oracle.run(spec, np.full(n, h0), np.full(n, q0), zf, 8, nthreads=2, lib=lib)
+        inner = slice(10, n - 10)
+        out["friction_steady"] = bool(np.max(np.abs(q1[inner] - q0)) < 1e-13 and
+                                      np.max(np.abs(h1[inner] - h0)) < 1e-13)
+    except oracle.OracleError:
+        out["friction_steady"] = False
+
+    # fixed-depth ghost: a run of one step equals one step with the ghost given explicitly
+    spec = oracle.ChannelSpec(n_cells=32, dx=0.1, Ag=0.01, porosity=0.4,
+                              bc_right=oracle.BC_FIXED_DEPTH, h_out=0.9)
+    hb = 1.0 + 0.05 * rng.uniform(-1, 1, 32)
+    qb = 0.3 + 0.02 * rng.uniform(-1, 1, 32)
+    zb = 0.01 * rng.uniform(-1, 1, 32)
+    try:
+        hr, qr, zr, _ = oracle.run(spec, hb, qb, zb, 1, nthreads=2, lib=lib)
+        am = oracle.cfl_amax(hb, qb, zb, G, 1 / 0.6, 0.01, lib=lib)
+        hs, qs2, zs = oracle.step(hb, qb, zb, [hb[0], qb[0], zb[0]], [0.9, qb[-1], zb[-1]], G, 1 / 0.6,
+                                  0.01, 3, 0.9 * 0.1 / am, 0.1, lib=lib)
+        out["fixed_depth"] = bool(np.array_equal(hr, hs) and np.array_equal(qr, qs2))
+    except oracle.OracleError:
+        out["fixed_depth"] = False
+
     for name, wl, periodic in (("scheme_c1", inputs.make_c1(n_cells=120, steps=25), False),
                                ("scheme_periodic", inputs.make_c2(n_cells=256, steps=25), True)):
         xi_c = 1.0 / (1.0 - wl.porosity[0])

@@ -47,6 +47,18 @@ MUTANTS = {
     "update_z_uses_q_row": ("c->Dm[2 * E + i + 1] + c->Dp[2 * E + i]", "c->Dm[1 * E + i + 1] + c->Dp[2 * E + i]"),
     "dt_without_cfl": ("double dt = ch->cfl * ch->dx / amax;", "double dt = ch->dx / amax;"),
     "amax_ignores_lambda3": ("if (fabs(lam[2]) > a) a = fabs(lam[2]);", ""),
+    "grass_thr_no_threshold": ("double ex = fabs(u) - p->par[0];", "double ex = fabs(u);"),
+    "power_exponent": ("pow(fabs(u), beta - 1.0)", "pow(fabs(u), beta)"),
+    "mpm_h_exponent": ("*dqs_dh = sign_of(q) * dqs_dtheta * (-7.0 / 3.0) * theta / h;",
+                       "*dqs_dh = sign_of(q) * dqs_dtheta * (-10.0 / 3.0) * theta / h;"),
+    "mpm_q_factor": ("*dqs_dq = dqs_dtheta * 2.0 * theta / fabs(q);",
+                     "*dqs_dq = dqs_dtheta * theta / fabs(q);"),
+    "vanrijn_exponent": ("pow(T, 1.1)", "pow(T, 2.1)"),
+    "vanrijn_dstar_nu": ("cbrt(p->g * (Sg - 1.0) / (nu * nu))", "cbrt(p->g * (Sg - 1.0) / nu)"),
+    "friction_sign": ("c->dt * (-c->p.g * c->h[i] * friction_slope", "c->dt * (c->p.g * c->h[i] * friction_slope"),
+    "friction_h_power": ("return q * fabs(q) / (ks * ks * pow(h, 10.0 / 3.0));",
+                         "return q * fabs(q) / (ks * ks * pow(h, 7.0 / 3.0));"),
+    "fixed_depth_ghost": ("case OR_BC_FIXED_DEPTH: gr[0] = ch->h_out;", "case OR_BC_FIXED_DEPTH: gr[0] = h[N - 1];"),
     "periodic_ghost_wrong_end": ("case OR_BC_PERIODIC: gl[0] = h[N - 1]; gl[1] = q[N - 1]; gl[2] = z[N - 1];",
                                  "case OR_BC_PERIODIC: gl[0] = h[0]; gl[1] = q[0]; gl[2] = z[0];"),
 }
