@@ -153,7 +153,10 @@ def cpu_baseline(wl, budget_s: float = 12.0):
     specs = [oracle.ChannelSpec(n_cells=int(sample.lengths()[c]), dx=float(sample.dx[c]),
                                 Ag=float(sample.Ag[c]), porosity=float(sample.porosity[c]), g=wl.g,
                                 n_gauss=wl.n_gauss, cfl=wl.cfl, bc_left=int(sample.bc_left[c]),
-                                bc_right=int(sample.bc_right[c]), q_in=float(sample.q_in[c]))
+                                bc_right=int(sample.bc_right[c]), q_in=float(sample.q_in[c]),
+                                h_in=float(sample.h_in[c]), h_out=float(sample.h_out[c]),
+                                law=int(sample.law), par=tuple(float(v) for v in sample.law_par[c]),
+                                ks=float(sample.ks[c]))
              for c in range(sample.n_channels)]
 
     def run(n):

@@ -5,13 +5,16 @@
  * Method (Carraro, Valiani, Caleffi, "Efficient analytical implementation of
  * the DOT Riemann solver for the de Saint Venant-Exner morphodynamic model"):
  *   state per cell W = (h, q, z): water depth, unit discharge, bed elevation
- *   (Sec. 2, Eq. W&A_definition); Grass bed load q_s = A_g u^3 (Sec. 2, Eq. Grass);
+ *   (Sec. 2, Eq. W&A_definition); bed load q_s(h, q) from one of the closures of
+ *   Sec. 2 (Eqs. Grass, GrassThr, MPM with Shields, vanRijn with u_star) or the
+ *   power law of Sec. 5.1 (Eq. Soni_qs);
  *   DOT fluctuations D^{+-} = 1/2 sum_k w_k (A(Psi_k) +- |A(Psi_k)|)(W+ - W-)
  *   on the segment path with a G-point Gauss-Legendre rule (Sec. 3.1, Eqs. path,
  *   DOTjumpN), |A| = R |Lambda| R^-1 from the closed-form eigenstructure
  *   (Sec. 3.3, Eqs. lambda, parameters, RR, RR-1, ExAbsA); first-order update
- *   W_i <- W_i - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) with no source term
- *   (Sec. 3, Eq. scheme; friction neglected as in Sec. 4);
+ *   W_i <- W_i - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i) (Sec. 3, Eq. scheme)
+ *   with S = (0, -g h s_f, 0), s_f = q|q| / (K_s^2 h^(10/3)) (Sec. 2) when a
+ *   Strickler coefficient K_s is given, S = 0 otherwise (as in Sec. 4);
  *   dt = CFL dx / max_i max_m |lambda_m(W_i)|.
  *
  * Conventions shared by every entry point:
@@ -40,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DSVE_ABI_VERSION 1
+#define DSVE_ABI_VERSION 2
 
 typedef struct dsve_ctx dsve_ctx;
 
@@ -50,24 +53,54 @@ typedef enum {
     DSVE_E_HIP = -2,            /* a HIP runtime call failed */
     DSVE_E_NONFINITE = -3,      /* a CFL speed was NaN/Inf or zero (e.g. h <= 0, coalescing roots) */
     DSVE_E_NONHYPERBOLIC = -4,  /* arccos argument outside [-1-1e-12, 1+1e-12] or k1 <= 0 */
-    DSVE_E_UNSUPPORTED = -5     /* valid but not implemented (e.g. another bed-load law) */
+    DSVE_E_UNSUPPORTED = -5     /* a valid request this build does not implement */
 } dsve_status;
 
-enum { DSVE_BC_TRANSMISSIVE = 0, DSVE_BC_PERIODIC = 1, DSVE_BC_INFLOW_Q = 2 };
-enum { DSVE_LAW_GRASS = 0 };
+/* Boundary conditions: the ghost state W_{-1} (left) or W_N (right), from the adjacent cell
+ * W_a = (h_a, q_a, z_a):
+ *   TRANSMISSIVE  W_a
+ *   PERIODIC      the cell at the other end (must be set on both sides)
+ *   INFLOW_Q      (h_a, q_in, z_a): imposed discharge
+ *   FIXED_DEPTH   (h_out, q_a, z_a): imposed depth, e.g. a downstream control (Sec. 5.1, 5.2)
+ *   INFLOW_QH     (h_in, q_in, z_a): imposed discharge and depth; an imposed solid discharge
+ *                 enters as the depth at which the closure gives it for q_in (Sec. 5.1) */
+enum { DSVE_BC_TRANSMISSIVE = 0, DSVE_BC_PERIODIC = 1, DSVE_BC_INFLOW_Q = 2,
+       DSVE_BC_FIXED_DEPTH = 3, DSVE_BC_INFLOW_QH = 4 };
+
+/* Bed-load closures q_s(h, q), u = q/h, acting in the direction of the flow.  law_extra[]
+ * holds the law's parameters; entries a law does not use must be zero.
+ *   GRASS      q_s = A_g u^3                        (Sec. 2, Eq. Grass)     no parameters
+ *   GRASS_THR  q_s = A_g sign(u) (|u| - u_cr)^3 for |u| > u_cr, else 0
+ *                                                   (Sec. 2, Eq. GrassThr)  [0] = u_cr >= 0
+ *   POWER      q_s = A_g sign(u) |u|^beta           (Sec. 5.1, Eq. Soni_qs) [0] = beta >= 1
+ *   MPM        q_s = sign(q) 8 (theta - 0.047)^(3/2) sqrt(g (S_g-1) d50^3) for theta > 0.047,
+ *              theta = s_f h / ((S_g-1) d50) with |s_f| (Sec. 2, Eqs. MPM, Shields)
+ *                                                   [0] = d50 > 0, [1] = S_g > 1; needs ks > 0
+ *   VANRIJN    q_s = sign(q) 0.053 T^2.1 / D_*^0.3 sqrt(g (S_g-1) d50^3) for T > 0,
+ *              T = u_*^2 / u_*cr^2 - 1, u_*^2 = g h |s_f|, u_*cr^2 = theta_cr g (S_g-1) d50,
+ *              D_* = d50 (g (S_g-1) / nu^2)^(1/3)    (Sec. 2, Eqs. vanRijn, u_star)
+ *                                                   [0] = d50 > 0, [1] = S_g > 1, [2] = nu > 0,
+ *                                                   [3] = theta_cr > 0; needs ks > 0
+ * A_g is used by GRASS, GRASS_THR and POWER and must be zero for MPM and VANRIJN. */
+enum { DSVE_LAW_GRASS = 0, DSVE_LAW_GRASS_THR = 1, DSVE_LAW_POWER = 2, DSVE_LAW_MPM = 3,
+       DSVE_LAW_VANRIJN = 4 };
 enum { DSVE_FP64 = 0, DSVE_MIXED = 1 };
 
-/* Parameters common to a context.
+/* Parameters of a context.
  *   g          gravitational acceleration (> 0)
  *   porosity   bed porosity p in [0, 1); xi = 1/(1-p)  (Sec. 2)
- *   law        DSVE_LAW_GRASS (q_s = A_g u^3, Sec. 2 Eq. Grass)
- *   A_g        Grass coefficient (>= 0)
- *   law_extra  reserved for further closures, must be zero
+ *   law        DSVE_LAW_* (the closure of q_s)
+ *   A_g        coefficient of the Grass-type laws (>= 0)
+ *   law_extra  parameters of the law (see DSVE_LAW_*)
  *   n_gauss    quadrature points G in [1, 5] (Sec. 3.1 Eq. DOTjumpN); 3 is the default
  *   cfl        Courant number in (0, 1]
  *   dx         cell width (> 0)
- *   bc_left, bc_right   DSVE_BC_*; periodic must be set on both sides
- *   q_in       unit discharge imposed by DSVE_BC_INFLOW_Q (ghost = (h_adjacent, q_in, z_adjacent))
+ *   bc_left, bc_right   DSVE_BC_*
+ *   q_in       unit discharge imposed by INFLOW_Q and INFLOW_QH
+ *   h_in       depth imposed by INFLOW_QH (> 0 when used)
+ *   h_out      depth imposed by FIXED_DEPTH (> 0 when used)
+ *   ks         Strickler coefficient K_s of the friction slope (>= 0; 0 = no friction source;
+ *              MPM and VANRIJN need ks > 0, their Shields stress and shear velocity use s_f)
  *   precision  DSVE_FP64: all arithmetic in FP64.
  *              DSVE_MIXED: eigenstructure and quadrature in FP32; FP64 for the
  *              jumps W+ - W-, for the cubic's root solve and the eigenvector
@@ -85,7 +118,23 @@ typedef struct {
     int bc_left, bc_right;
     double q_in;
     int precision;
+    double h_in;
+    double h_out;
+    double ks;
 } dsve_params;
+
+/* Per-channel parameters of a batched context (meaning and ranges as in dsve_params). */
+typedef struct {
+    double A_g;
+    double porosity;
+    double dx;
+    double q_in;
+    double h_in;
+    double h_out;
+    double ks;
+    double law_extra[4];
+    int bc_left, bc_right;
+} dsve_channel;
 
 /* Library ABI version (DSVE_ABI_VERSION). */
 int dsve_abi_version(void);
@@ -97,18 +146,16 @@ int dsve_abi_version(void);
 dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, void *hip_stream);
 
 /* Create a context for n_channels independent channels (n_channels >= 1).
- * HOST arrays, all of length n_channels unless stated:
+ * HOST arrays:
  *   offsets[n_channels+1]  cell offsets, offsets[0] = 0, strictly increasing
- *   A_g, porosity, dx      per-channel parameters (ranges as in dsve_params)
- *   bc_left, bc_right      per-channel boundary conditions
- *   q_in                   per-channel inflow discharge (may be NULL: zero)
- * Everything else (g, law, n_gauss, cfl, precision) comes from *common; the
- * per-channel fields of *common (A_g, porosity, dx, bc_*, q_in) are ignored.
- * Each channel gets its own time step and clock (Sec. 3, Eq. scheme per channel). */
+ *   channels[n_channels]   per-channel parameters (each checked as in dsve_params)
+ * g, law, n_gauss, cfl and precision come from *common; its per-channel fields (A_g,
+ * porosity, dx, bc_*, q_in, h_in, h_out, ks, law_extra) are ignored.  All channels share the
+ * closure law; its parameters may differ per channel.  Each channel gets its own time step
+ * and clock (Sec. 3, Eq. scheme per channel).  The arrays are copied; the caller keeps them. */
 dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *offsets,
-                            const double *A_g, const double *porosity, const double *dx,
-                            const int *bc_left, const int *bc_right, const double *q_in,
-                            const dsve_params *common, void *hip_stream);
+                            const dsve_channel *channels, const dsve_params *common,
+                            void *hip_stream);
 
 /* Release the context and its device scratch (waits for its queued work). */
 dsve_status dsve_destroy(dsve_ctx *ctx);
@@ -122,11 +169,11 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
                            const double *hR, const double *qR, const double *zR, int64_t n,
                            double *Dm, double *Dp);
 
-/* Cell update of one channel (Sec. 3, Eq. scheme, S = 0): for i = 0..N-1,
- *   W_i <- W_i - (dt/dx) (Dm[:, i+1] + Dp[:, i])
+/* Cell update of one channel (Sec. 3, Eq. scheme): for i = 0..N-1,
+ *   W_i <- W_i - (dt/dx) (Dm[:, i+1] + Dp[:, i]) + dt S(W_i)
  * with Dm, Dp the [3][N+1] edge fluctuations (edge i is the left face of cell i),
- * dt_dev a device pointer to the time step, and h, q, z updated in place.
- * Single-channel contexts only. */
+ * dt_dev a device pointer to the time step, S the friction source of the context (zero
+ * when ks = 0), and h, q, z updated in place.  Single-channel contexts only. */
 dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const double *dt_dev,
                         double *h, double *q, double *z);
 
@@ -140,7 +187,7 @@ dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const do
 
 /* Advance one channel by n_steps >= 0 time steps in place: per step, ghost
  * cells from the boundary conditions, dt = cfl*dx/amax(W^n), DOT fluctuations
- * at every edge, cell update, and the CFL speed of W^{n+1} for the next step --
+ * at every edge, cell update with the friction source, and the CFL speed of W^{n+1} --
  * one fused kernel per step, replayed from a HIP graph.  *t_dev (device) is
  * increased by the sum of the time steps.  The result is in (h, q, z) when the
  * enqueued work completes, bitwise independent of the launch configuration. */

@@ -31,6 +31,7 @@ BC_TRANSMISSIVE = 0
 BC_PERIODIC = 1
 BC_INFLOW_Q = 2
 BC_FIXED_DEPTH = 3
+BC_INFLOW_QH = 4
 
 LAW_GRASS = 0       # q_s = A_g u^3                                   (Sec. 2, Eq. Grass)
 LAW_GRASS_THR = 1   # q_s = A_g (u - u_cr)^3, par = (u_cr,)           (Sec. 2, Eq. GrassThr)
@@ -65,6 +66,7 @@ class Channel(ctypes.Structure):
         ("bc_right", ctypes.c_int),
         ("q_in", ctypes.c_double),
         ("h_out", ctypes.c_double),
+        ("h_in", ctypes.c_double),
         ("law", ctypes.c_int),
         ("par", ctypes.c_double * 4),
         ("ks", ctypes.c_double),
@@ -237,6 +239,7 @@ class ChannelSpec:
     bc_right: int = BC_TRANSMISSIVE
     q_in: float = 0.0
     h_out: float = 0.0
+    h_in: float = 0.0
     law: int = LAW_GRASS
     par: tuple = ()
     ks: float = 0.0
@@ -245,7 +248,7 @@ class ChannelSpec:
         pr = list(self.par) + [0.0] * (4 - len(self.par))
         return Channel(self.n_cells, self.g, 1.0 / (1.0 - self.porosity), self.Ag, self.n_gauss,
                        self.cfl, self.dx, self.bc_left, self.bc_right, self.q_in, self.h_out,
-                       self.law, (ctypes.c_double * 4)(*pr), self.ks)
+                       self.h_in, self.law, (ctypes.c_double * 4)(*pr), self.ks)
 
 
 def run(spec: ChannelSpec, h, q, z, n_steps: int, t0: float = 0.0, nthreads: int | None = None,

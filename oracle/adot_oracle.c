@@ -45,6 +45,7 @@
 #define OR_BC_PERIODIC 1
 #define OR_BC_INFLOW_Q 2
 #define OR_BC_FIXED_DEPTH 3
+#define OR_BC_INFLOW_QH 4
 
 #define OR_LAW_GRASS 0
 #define OR_LAW_GRASS_THR 1
@@ -86,6 +87,7 @@ typedef struct {
     int bc_left, bc_right;
     double q_in;  /* discharge imposed by an inflow-q boundary */
     double h_out; /* depth imposed by a fixed-depth boundary */
+    double h_in;  /* depth imposed with q_in by an inflow-(q, h) boundary */
     int law;
     double par[4];
     double ks;
@@ -617,7 +619,9 @@ int or_step(int64_t N, const double *h, const double *q, const double *z, const 
 /* Ghost states from the boundary conditions (reading: the paper does not spell
  * out the ghost-cell form):  transmissive = copy of the adjacent cell;
  * periodic = the cell at the other end; inflow-q = (h, q_in, z) of the adjacent cell;
- * fixed depth = (h_out, q, z) of the adjacent cell. */
+ * fixed depth = (h_out, q, z) of the adjacent cell; inflow-(q, h) = (h_in, q_in, z) of the
+ * adjacent cell (an imposed solid discharge enters through the depth h_in at which the
+ * closure gives that q_s for q_in, Sec. 5.1). */
 static void ghost_states(const or_channel *ch, const double *h, const double *q, const double *z,
                          double gl[3], double gr[3])
 {
@@ -626,12 +630,14 @@ static void ghost_states(const or_channel *ch, const double *h, const double *q,
     case OR_BC_PERIODIC: gl[0] = h[N - 1]; gl[1] = q[N - 1]; gl[2] = z[N - 1]; break;
     case OR_BC_INFLOW_Q: gl[0] = h[0]; gl[1] = ch->q_in; gl[2] = z[0]; break;
     case OR_BC_FIXED_DEPTH: gl[0] = ch->h_out; gl[1] = q[0]; gl[2] = z[0]; break;
+    case OR_BC_INFLOW_QH: gl[0] = ch->h_in; gl[1] = ch->q_in; gl[2] = z[0]; break;
     default: gl[0] = h[0]; gl[1] = q[0]; gl[2] = z[0]; break;
     }
     switch (ch->bc_right) {
     case OR_BC_PERIODIC: gr[0] = h[0]; gr[1] = q[0]; gr[2] = z[0]; break;
     case OR_BC_INFLOW_Q: gr[0] = h[N - 1]; gr[1] = ch->q_in; gr[2] = z[N - 1]; break;
     case OR_BC_FIXED_DEPTH: gr[0] = ch->h_out; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
+    case OR_BC_INFLOW_QH: gr[0] = ch->h_in; gr[1] = ch->q_in; gr[2] = z[N - 1]; break;
     default: gr[0] = h[N - 1]; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
     }
 }
@@ -641,7 +647,7 @@ static int check_channel(const or_channel *ch)
     if (ch->n_cells < 1) return OR_E_ARG;
     if (ch->n_gauss < 1 || ch->n_gauss > 64) return OR_E_ARG;
     if (!(ch->cfl > 0.0) || !(ch->dx > 0.0) || !(ch->g > 0.0) || !(ch->xi >= 1.0)) return OR_E_ARG;
-    if (ch->bc_left < 0 || ch->bc_left > 3 || ch->bc_right < 0 || ch->bc_right > 3) return OR_E_ARG;
+    if (ch->bc_left < 0 || ch->bc_left > 4 || ch->bc_right < 0 || ch->bc_right > 4) return OR_E_ARG;
     if ((ch->bc_left == OR_BC_PERIODIC) != (ch->bc_right == OR_BC_PERIODIC)) return OR_E_ARG;
     if (ch->law < OR_LAW_GRASS || ch->law > OR_LAW_VANRIJN) return OR_E_ARG;
     if ((ch->law == OR_LAW_MPM || ch->law == OR_LAW_VANRIJN) && !(ch->ks > 0.0)) return OR_E_ARG;

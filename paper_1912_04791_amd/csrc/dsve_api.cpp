@@ -33,6 +33,8 @@ struct dsve_ctx {
     bool batched = false;
 
     int precision = DSVE_FP64;
+    int law = DSVE_LAW_GRASS;
+    int cl = CL_GRASS;   // kernel closure form
     int G = 3;
     double g = 9.81;
     double cfl = 0.9;
@@ -43,7 +45,6 @@ struct dsve_ctx {
     ChanInfo *d_ch = nullptr;
     int64_t *d_off = nullptr, *d_eoff = nullptr;
     GaussRule rule{};
-    double h_dx0 = 1.0;   // dx of channel 0 (the cell_update entry point divides by it)
 
     double *pp_h = nullptr, *pp_q = nullptr, *pp_z = nullptr;   // ping-pong copy
     unsigned long long *d_amax = nullptr;                        // [3][C]
@@ -118,30 +119,59 @@ static bool gauss_rule(int G, GaussRule &r)
     return true;
 }
 
-static bool valid_bc(int b) { return b == DSVE_BC_TRANSMISSIVE || b == DSVE_BC_PERIODIC || b == DSVE_BC_INFLOW_Q; }
+static bool valid_bc(int b) { return b >= DSVE_BC_TRANSMISSIVE && b <= DSVE_BC_INFLOW_QH; }
 
 static dsve_status check_common(const dsve_params *p, std::string &msg)
 {
     if (!p) { msg = "params is NULL"; return DSVE_E_ARG; }
     if (!(p->g > 0.0) || !std::isfinite(p->g)) { msg = "g must be > 0"; return DSVE_E_ARG; }
-    if (p->law != DSVE_LAW_GRASS) { msg = "only the Grass law is implemented"; return DSVE_E_UNSUPPORTED; }
-    for (double v : p->law_extra)
-        if (v != 0.0) { msg = "law_extra must be zero for the Grass law"; return DSVE_E_ARG; }
+    if (p->law < DSVE_LAW_GRASS || p->law > DSVE_LAW_VANRIJN) { msg = "unknown law"; return DSVE_E_ARG; }
     if (p->n_gauss < 1 || p->n_gauss > 5) { msg = "n_gauss must be in [1, 5]"; return DSVE_E_ARG; }
     if (!(p->cfl > 0.0 && p->cfl <= 1.0)) { msg = "cfl must be in (0, 1]"; return DSVE_E_ARG; }
     if (p->precision != DSVE_FP64 && p->precision != DSVE_MIXED) { msg = "unknown precision"; return DSVE_E_ARG; }
     return DSVE_OK;
 }
 
-static dsve_status check_channel(double Ag, double por, double dx, int bcl, int bcr, double q_in,
-                                 std::string &msg)
+static bool pos(double v) { return v > 0.0 && std::isfinite(v); }
+
+static dsve_status check_channel(int law, const dsve_channel &ch, std::string &msg)
 {
-    if (!(Ag >= 0.0) || !std::isfinite(Ag)) { msg = "A_g must be finite and >= 0"; return DSVE_E_ARG; }
-    if (!(por >= 0.0 && por < 1.0)) { msg = "porosity must be in [0, 1)"; return DSVE_E_ARG; }
-    if (!(dx > 0.0) || !std::isfinite(dx)) { msg = "dx must be > 0"; return DSVE_E_ARG; }
-    if (!valid_bc(bcl) || !valid_bc(bcr)) { msg = "unknown boundary condition"; return DSVE_E_ARG; }
-    if ((bcl == DSVE_BC_PERIODIC) != (bcr == DSVE_BC_PERIODIC)) { msg = "periodic must be set on both sides"; return DSVE_E_ARG; }
-    if (!std::isfinite(q_in)) { msg = "q_in must be finite"; return DSVE_E_ARG; }
+    if (!(ch.A_g >= 0.0) || !std::isfinite(ch.A_g)) { msg = "A_g must be finite and >= 0"; return DSVE_E_ARG; }
+    if (!(ch.porosity >= 0.0 && ch.porosity < 1.0)) { msg = "porosity must be in [0, 1)"; return DSVE_E_ARG; }
+    if (!pos(ch.dx)) { msg = "dx must be > 0"; return DSVE_E_ARG; }
+    if (!valid_bc(ch.bc_left) || !valid_bc(ch.bc_right)) { msg = "unknown boundary condition"; return DSVE_E_ARG; }
+    if ((ch.bc_left == DSVE_BC_PERIODIC) != (ch.bc_right == DSVE_BC_PERIODIC)) { msg = "periodic must be set on both sides"; return DSVE_E_ARG; }
+    if (!std::isfinite(ch.q_in)) { msg = "q_in must be finite"; return DSVE_E_ARG; }
+    const bool uses_hin = ch.bc_left == DSVE_BC_INFLOW_QH || ch.bc_right == DSVE_BC_INFLOW_QH;
+    const bool uses_hout = ch.bc_left == DSVE_BC_FIXED_DEPTH || ch.bc_right == DSVE_BC_FIXED_DEPTH;
+    if (uses_hin && !pos(ch.h_in)) { msg = "h_in must be > 0 for an inflow-(q, h) boundary"; return DSVE_E_ARG; }
+    if (uses_hout && !pos(ch.h_out)) { msg = "h_out must be > 0 for a fixed-depth boundary"; return DSVE_E_ARG; }
+    if (!(ch.ks >= 0.0) || !std::isfinite(ch.ks)) { msg = "ks must be finite and >= 0"; return DSVE_E_ARG; }
+    const double *x = ch.law_extra;
+    int used = 0;
+    switch (law) {
+    case DSVE_LAW_GRASS: used = 0; break;
+    case DSVE_LAW_GRASS_THR:
+        used = 1;
+        if (!(x[0] >= 0.0) || !std::isfinite(x[0])) { msg = "u_cr must be finite and >= 0"; return DSVE_E_ARG; }
+        break;
+    case DSVE_LAW_POWER:
+        used = 1;
+        if (!(x[0] >= 1.0) || !std::isfinite(x[0])) { msg = "beta must be finite and >= 1"; return DSVE_E_ARG; }
+        break;
+    case DSVE_LAW_MPM:
+    case DSVE_LAW_VANRIJN:
+        used = law == DSVE_LAW_MPM ? 2 : 4;
+        if (!pos(x[0])) { msg = "d50 must be > 0"; return DSVE_E_ARG; }
+        if (!(x[1] > 1.0) || !std::isfinite(x[1])) { msg = "S_g must be > 1"; return DSVE_E_ARG; }
+        if (law == DSVE_LAW_VANRIJN && (!pos(x[2]) || !pos(x[3]))) { msg = "nu and theta_cr must be > 0"; return DSVE_E_ARG; }
+        if (!(ch.ks > 0.0)) { msg = "this law needs a Strickler coefficient ks > 0"; return DSVE_E_ARG; }
+        if (ch.A_g != 0.0) { msg = "A_g must be zero for this law"; return DSVE_E_ARG; }
+        break;
+    default: msg = "unknown law"; return DSVE_E_ARG;
+    }
+    for (int k = used; k < 4; ++k)
+        if (x[k] != 0.0) { msg = "unused law_extra entries must be zero"; return DSVE_E_ARG; }
     return DSVE_OK;
 }
 
@@ -227,22 +257,81 @@ static void release(dsve_ctx *c)
     delete c;
 }
 
-static ChanInfo make_chan(int64_t cell0, int64_t n, double Ag, double por, double dx, int bcl,
-                          int bcr, double q_in, double cfl, double g)
+static ChanInfo make_chan(int64_t cell0, int64_t n, int law, const dsve_channel &ch, double cfl,
+                          double g)
 {
     ChanInfo ci{};
     ci.cell0 = cell0;
     ci.ncell = n;
-    const double xi = 1.0 / (1.0 - por);
-    ci.kqg = 3.0 * xi * Ag * g;
+    const double xi = 1.0 / (1.0 - ch.porosity);
+    ci.kqg = 3.0 * xi * ch.A_g * g;
     ci.K1 = 1.0 + 3.0 * ci.kqg;
     ci.K2 = 2.0 + 9.0 * ci.kqg;
-    ci.cfl_dx = cfl * dx;
-    ci.inv_dx = 1.0 / dx;
-    ci.q_in = q_in;
-    ci.bcl = bcl;
-    ci.bcr = bcr;
+    ci.cfl_dx = cfl * ch.dx;
+    ci.inv_dx = 1.0 / ch.dx;
+    ci.q_in = ch.q_in;
+    ci.h_in = ch.h_in;
+    ci.h_out = ch.h_out;
+    ci.fric = ch.ks > 0.0 ? 1.0 / (ch.ks * ch.ks) : 0.0;
+    ci.law = law;
+    const double *x = ch.law_extra;
+    switch (law) {
+    case DSVE_LAW_GRASS:
+        ci.lp0 = 3.0 * xi * ch.A_g;
+        break;
+    case DSVE_LAW_GRASS_THR:
+        ci.lp0 = 3.0 * xi * ch.A_g;
+        ci.lp1 = x[0];
+        break;
+    case DSVE_LAW_POWER:
+        ci.lp0 = xi * ch.A_g * x[0];
+        ci.lp1 = x[0] - 1.0;
+        break;
+    case DSVE_LAW_MPM: {
+        const double d50 = x[0], sg1 = x[1] - 1.0;
+        ci.lp0 = 1.0 / (ch.ks * ch.ks * sg1 * d50);
+        ci.lp1 = 24.0 * xi * std::sqrt(g * sg1 * d50 * d50 * d50);
+        break;
+    }
+    case DSVE_LAW_VANRIJN: {
+        const double d50 = x[0], sg1 = x[1] - 1.0, nu = x[2], theta_cr = x[3];
+        const double uscr2 = theta_cr * g * sg1 * d50;
+        const double dstar = d50 * std::cbrt(g * sg1 / (nu * nu));
+        ci.lp0 = g / (ch.ks * ch.ks * uscr2);
+        ci.lp1 = 4.2 * xi * 0.053 / std::pow(dstar, 0.3) * std::sqrt(g * sg1 * d50 * d50 * d50);
+        break;
+    }
+    default: break;
+    }
+    ci.bcl = ch.bc_left;
+    ci.bcr = ch.bc_right;
     return ci;
+}
+
+static dsve_channel channel_of(const dsve_params *p)
+{
+    dsve_channel ch{};
+    ch.A_g = p->A_g;
+    ch.porosity = p->porosity;
+    ch.dx = p->dx;
+    ch.q_in = p->q_in;
+    ch.h_in = p->h_in;
+    ch.h_out = p->h_out;
+    ch.ks = p->ks;
+    for (int k = 0; k < 4; ++k) ch.law_extra[k] = p->law_extra[k];
+    ch.bc_left = p->bc_left;
+    ch.bc_right = p->bc_right;
+    return ch;
+}
+
+static void set_common(dsve_ctx *c, const dsve_params *p)
+{
+    c->precision = p->precision;
+    c->law = p->law;
+    c->cl = p->law == DSVE_LAW_GRASS ? CL_GRASS : CL_LAW;
+    c->G = p->n_gauss;
+    c->g = p->g;
+    c->cfl = p->cfl;
 }
 
 // ---------------------------------------------------------------------------
@@ -258,19 +347,15 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
     dsve_status st = check_common(p, msg);
     if (st != DSVE_OK) return st;
     if (n_cells < 1) return DSVE_E_ARG;
-    st = check_channel(p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right, p->q_in, msg);
+    const dsve_channel ch = channel_of(p);
+    st = check_channel(p->law, ch, msg);
     if (st != DSVE_OK) return st;
     dsve_ctx *c = new dsve_ctx();
-    c->precision = p->precision;
-    c->G = p->n_gauss;
-    c->g = p->g;
-    c->cfl = p->cfl;
+    set_common(c, p);
     c->n_channels = 1;
     c->n_cells = n_cells;
     c->h_off = {0, n_cells};
-    c->h_ch.push_back(make_chan(0, n_cells, p->A_g, p->porosity, p->dx, p->bc_left, p->bc_right,
-                                p->q_in, p->cfl, p->g));
-    c->h_dx0 = p->dx;
+    c->h_ch.push_back(make_chan(0, n_cells, p->law, ch, p->cfl, p->g));
     st = setup(c, hip_stream);
     if (st != DSVE_OK) {
         release(c);
@@ -281,9 +366,8 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
 }
 
 dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *offsets,
-                            const double *A_g, const double *porosity, const double *dx,
-                            const int *bc_left, const int *bc_right, const double *q_in,
-                            const dsve_params *common, void *hip_stream)
+                            const dsve_channel *channels, const dsve_params *common,
+                            void *hip_stream)
 {
     if (!out) return DSVE_E_ARG;
     *out = nullptr;
@@ -291,27 +375,23 @@ dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *o
     dsve_status st = check_common(common, msg);
     if (st != DSVE_OK) return st;
     if (n_channels < 1 || n_channels > (int64_t)1 << 30) return DSVE_E_ARG;
-    if (!offsets || !A_g || !porosity || !dx || !bc_left || !bc_right) return DSVE_E_ARG;
+    if (!offsets || !channels) return DSVE_E_ARG;
     if (offsets[0] != 0) return DSVE_E_ARG;
     for (int64_t k = 0; k < n_channels; ++k) {
         if (offsets[k + 1] <= offsets[k]) return DSVE_E_ARG;
-        st = check_channel(A_g[k], porosity[k], dx[k], bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, msg);
+        st = check_channel(common->law, channels[k], msg);
         if (st != DSVE_OK) return st;
     }
     dsve_ctx *c = new dsve_ctx();
     c->batched = true;
-    c->precision = common->precision;
-    c->G = common->n_gauss;
-    c->g = common->g;
-    c->cfl = common->cfl;
+    set_common(c, common);
     c->n_channels = n_channels;
     c->n_cells = offsets[n_channels];
     c->h_off.assign(offsets, offsets + n_channels + 1);
     c->h_ch.reserve(n_channels);
     for (int64_t k = 0; k < n_channels; ++k)
-        c->h_ch.push_back(make_chan(offsets[k], offsets[k + 1] - offsets[k], A_g[k], porosity[k], dx[k],
-                                    bc_left[k], bc_right[k], q_in ? q_in[k] : 0.0, common->cfl,
-                                    common->g));
+        c->h_ch.push_back(make_chan(offsets[k], offsets[k + 1] - offsets[k], common->law, channels[k],
+                                    common->cfl, common->g));
     st = setup(c, hip_stream);
     if (st != DSVE_OK) {
         release(c);
@@ -355,7 +435,7 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
     a.hL = hL; a.qL = qL; a.zL = zL; a.hR = hR; a.qR = qR; a.zR = zR;
     a.Dm = Dm; a.Dp = Dp; a.flags = ctx->d_flags; a.n = n;
     a.g = ctx->g; a.ci = ctx->h_ch[0]; a.rule = ctx->rule;
-    HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->stream));
+    HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->cl, ctx->stream));
     return DSVE_OK;
 }
 
@@ -366,7 +446,7 @@ dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const
     if (ctx->sticky != DSVE_OK) return ctx->sticky;
     if (ctx->batched) return fail(ctx, DSVE_E_ARG, "cell_update needs a single-channel context");
     if (!Dm || !Dp || !dt_dev || !h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
-    HIP_TRY(ctx, launch_cell_update(Dm, Dp, dt_dev, 0.0, ctx->h_dx0, ctx->n_cells, h, q, z,
+    HIP_TRY(ctx, launch_cell_update(Dm, Dp, dt_dev, ctx->d_ch, ctx->g, ctx->n_cells, h, q, z,
                                     ctx->stream));
     return DSVE_OK;
 }
@@ -379,7 +459,7 @@ static dsve_status enqueue_cfl(dsve_ctx *ctx, const double *h, const double *q, 
     a.h = h; a.q = q; a.z = z; a.ch = ctx->d_ch; a.off = ctx->d_off; a.amax = amax;
     a.flags = ctx->d_flags; a.n_cells = ctx->n_cells; a.n_channels = (int32_t)ctx->n_channels;
     a.g = ctx->g;
-    HIP_TRY(ctx, launch_cfl(a, ctx->precision, ctx->stream));
+    HIP_TRY(ctx, launch_cfl(a, ctx->precision, ctx->cl, ctx->stream));
     return DSVE_OK;
 }
 
@@ -434,7 +514,7 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
 static int grid_of(const dsve_ctx *ctx)
 {
     const int bpc = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
-                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->tile);
+                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->cl, ctx->tile);
     return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)bpc * ctx->cus);
 }
 
@@ -449,8 +529,8 @@ static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, 
     hipGraph_t graph = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < ctx->graph_steps; ++j) {
-        hipError_t e = launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->tile,
-                                   grid, ctx->cap_stream);
+        hipError_t e = launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
+                                   ctx->tile, grid, ctx->cap_stream);
         if (e != hipSuccess) {
             (void)hipStreamEndCapture(ctx->cap_stream, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -495,8 +575,8 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
     }
     const int grid = grid_of(ctx);
     for (int j = done; j < n_steps; ++j)
-        HIP_TRY(ctx, launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->tile, grid,
-                                 ctx->stream));
+        HIP_TRY(ctx, launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
+                                 ctx->tile, grid, ctx->stream));
     if (n_steps % 2) {
         const size_t bytes = sizeof(double) * ctx->n_cells;
         HIP_TRY(ctx, hipMemcpyAsync(h, ctx->pp_h, bytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -592,7 +672,7 @@ static std::string tune_key(const dsve_ctx *ctx)
         ++hist[b];
     }
     std::ostringstream os;
-    os << ctx->arch << "|cu" << ctx->cus << "|p" << ctx->precision << "|G" << ctx->G << "|C"
+    os << ctx->arch << "|cu" << ctx->cus << "|p" << ctx->precision << "|law" << ctx->law << "|G" << ctx->G << "|C"
        << ctx->n_channels << "|N" << ctx->n_cells << "|h";
     for (int b = 0; b < 40; ++b)
         if (hist[b]) os << b << ":" << hist[b] << ",";

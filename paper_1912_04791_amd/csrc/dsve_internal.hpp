@@ -3,8 +3,8 @@
 // Layout in HBM (all device memory):
 //   state      h[N], q[N], z[N] float64 SoA, channels back to back (caller's arrays
 //              plus one ping-pong copy owned by the context)
-//   ChanInfo   one 96-byte record per channel (offsets, closure constants, CFL constant,
-//              1/dx, boundary conditions)
+//   ChanInfo   one 128-byte record per channel (offsets, closure constants, CFL constant,
+//              1/dx, friction, boundary conditions)
 //   eoff       int64 [C+1]: first edge of each channel in the flat edge space;
 //              channel c has N_c + 1 edges, eoff[c] = off[c] + c, eoff[C] = total edges
 //   tile_chan  int32 per tile: channel of the tile's first edge
@@ -18,8 +18,12 @@
 
 namespace dsve {
 
-enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2 };
+enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2, BC_FIXED_DEPTH = 3, BC_INFLOW_QH = 4 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
+enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN = 4 };
+// Kernel variants by closure: the Grass law in closed non-dimensional form, or any law through
+// the per-state coefficient b = xi dq_s/dq.
+enum { CL_GRASS = 0, CL_LAW = 1 };
 
 constexpr int kMaxGauss = 5;
 constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most
@@ -30,7 +34,29 @@ constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step
 #ifndef DSVE_MINW_MIXED
 #define DSVE_MINW_MIXED 4
 #endif
+// The general-closure variants carry the laws' power and root evaluations: fewer waves, more
+// registers per lane.
+#ifndef DSVE_MINW_LAW_FP64
+#define DSVE_MINW_LAW_FP64 2
+#endif
+#ifndef DSVE_MINW_LAW_MIXED
+#define DSVE_MINW_LAW_MIXED 2
+#endif
+constexpr int step_min_waves(int prec, int cl)
+{
+    return cl == CL_GRASS ? (prec == PREC_FP64 ? DSVE_MINW_FP64 : DSVE_MINW_MIXED)
+                          : (prec == PREC_FP64 ? DSVE_MINW_LAW_FP64 : DSVE_MINW_LAW_MIXED);
+}
 
+// Law constants lp0, lp1 (b = xi dq_s/dq at a state with u = q/h, 1/h, |q|):
+//   GRASS      lp0 = 3 xi A_g                        b = lp0 u^2 / h
+//   GRASS_THR  lp0 = 3 xi A_g, lp1 = u_cr            b = lp0 (|u| - u_cr)^2 / h above u_cr
+//   POWER      lp0 = xi A_g beta, lp1 = beta - 1     b = lp0 |u|^lp1 / h
+//   MPM        lp0 = 1 / (K_s^2 (S_g-1) d50),        theta = lp0 u^2 / h^(1/3),
+//              lp1 = 24 xi sqrt(g (S_g-1) d50^3)     b = lp1 sqrt(theta - 0.047) theta / |q|
+//   VANRIJN    lp0 = g / (K_s^2 u_*cr^2),            T + 1 = lp0 u^2 / h^(1/3),
+//              lp1 = 4.2 xi 0.053 sqrt(g (S_g-1) d50^3) / D_*^0.3
+//                                                    b = lp1 T^1.1 (T + 1) / |q|
 struct alignas(16) ChanInfo {
     int64_t cell0;   // first cell of the channel in the concatenated state
     int64_t ncell;   // N_c
@@ -38,11 +64,16 @@ struct alignas(16) ChanInfo {
     double K1, K2;   // 1 + 3 kqg, 2 + 9 kqg (k1 = 3 + K1 Fr^2, k2 = Fr (18 - K2 Fr^2))
     double cfl_dx;   // cfl * dx  (dt = cfl_dx / amax)
     double inv_dx;   // 1 / dx
-    double q_in;     // inflow discharge for BC_INFLOW_Q
+    double q_in;     // discharge imposed by BC_INFLOW_Q / BC_INFLOW_QH
+    double h_in;     // depth imposed by BC_INFLOW_QH
+    double h_out;    // depth imposed by BC_FIXED_DEPTH
+    double fric;     // 1 / K_s^2 of the friction slope (0: no friction source)
+    double lp0, lp1; // law constants (above)
     int32_t bcl, bcr;
-    int32_t pad[6];
+    int32_t law;
+    int32_t pad;
 };
-static_assert(sizeof(ChanInfo) == 96, "ChanInfo layout changed");
+static_assert(sizeof(ChanInfo) == 128, "ChanInfo layout changed");
 
 struct GaussRule {
     double s[kMaxGauss];
@@ -90,14 +121,16 @@ struct FluctArgs {
 
 // Host-side launchers (dsve_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
-hipError_t launch_step(const StepArgs &a, int precision, int G, int tile, int grid,
+hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
                        hipStream_t stream);
 // Workgroups of the step kernel that fit on one compute unit at once (occupancy query).
-int step_blocks_per_cu(int precision, int G, int tile);
-hipError_t launch_cfl(const CflArgs &a, int precision, hipStream_t stream);
-hipError_t launch_fluct(const FluctArgs &a, int precision, int G, hipStream_t stream);
+int step_blocks_per_cu(int precision, int G, int cl, int tile);
+hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t stream);
+hipError_t launch_fluct(const FluctArgs &a, int precision, int G, int cl, hipStream_t stream);
+// Cell update of one channel from given fluctuations; ch is the channel's record on the device
+// (its 1/dx and friction coefficient are used).
 hipError_t launch_cell_update(const double *Dm, const double *Dp, const double *dt,
-                              double inv_dx_unused, double dx, int64_t N, double *h, double *q,
+                              const ChanInfo *ch, double g, int64_t N, double *h, double *q,
                               double *z, hipStream_t stream);
 hipError_t launch_dt(const unsigned long long *amax, const ChanInfo *ch, int32_t n_channels,
                      double *dt, hipStream_t stream);

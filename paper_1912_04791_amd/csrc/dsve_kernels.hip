@@ -8,6 +8,9 @@
 // k_fluct     pairwise fluctuations (dot_edge_fluct entry point).
 // k_update    cell update from given fluctuations (cell_update entry point).
 //
+// Every kernel comes in two closure forms: CL_GRASS (the Grass law in closed form, the
+// workloads of Sec. 4) and CL_LAW (any closure through b = xi dq_s/dq per state).
+//
 // Tiling of the step kernel: a workgroup of T threads takes T consecutive edges of the flat
 // edge space and updates the T-1 cells whose two faces both lie in the tile; tile k starts at
 // edge k (T-1), so consecutive tiles share one edge, which both compute.  Every cell is
@@ -59,28 +62,39 @@ __device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1u);
 }
 
-// Edge fluctuation and cell speed for the chosen precision.
-template <int G, int PREC>
+// Edge fluctuation and cell speed for the chosen precision and closure form.
+template <int G, int PREC, int CL>
 __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, double hR, double qR,
                                            double zR, double g, const Closure &K,
                                            const GaussRule &rule, double Dm[3], double Dp[3],
                                            bool &bad)
 {
-    if constexpr (PREC == PREC_FP64) fluct64<G>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
-    else fluct_mixed<G>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    if constexpr (PREC == PREC_FP64) fluct64<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    else fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
 }
 
-template <int PREC>
+template <int PREC, int CL>
 __device__ __forceinline__ double cell_speed(double h, double q, double g, const Closure &K,
                                              bool &bad)
 {
-    if constexpr (PREC == PREC_FP64) return speed64(h, q, g, K, bad);
-    else return speed_mixed(h, q, g, K, bad);
+    if constexpr (PREC == PREC_FP64) return speed64<CL>(h, q, g, K, bad);
+    else return speed_mixed<CL>(h, q, g, K, bad);
+}
+
+// Ghost states (boundary conditions): depth and discharge beyond edge 0 (left) or edge N
+// (right) of a channel from the adjacent cell's (h, q); the bed is always the adjacent cell's.
+__device__ __forceinline__ double ghost_h(int bc, const ChanInfo &ci, double h)
+{
+    return bc == BC_FIXED_DEPTH ? ci.h_out : (bc == BC_INFLOW_QH ? ci.h_in : h);
+}
+__device__ __forceinline__ double ghost_q(int bc, const ChanInfo &ci, double q)
+{
+    return (bc == BC_INFLOW_Q || bc == BC_INFLOW_QH) ? ci.q_in : q;
 }
 
 // ---------------------------------------------------------------------------
-template <int G, int PREC>
-__global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE_MINW_MIXED) void k_step(StepArgs A)
+template <int G, int PREC, int CL>
+__global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(StepArgs A)
 {
     extern __shared__ double s_dm[];          // [3][T]
     __shared__ unsigned long long s_acc;
@@ -107,16 +121,19 @@ __global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE
             const int64_t N = ci.ncell, base = ci.cell0;
             const int64_t il = (e == 0) ? (ci.bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
             const int64_t ir = (e == N) ? (ci.bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
-            const double hL = A.h[il];
+            double hL = A.h[il];
             double qL = A.q[il];
             const double zL = A.z[il];
             hR = A.h[ir];
             qR = A.q[ir];
             zR = A.z[ir];
-            if (e == 0 && ci.bcl == BC_INFLOW_Q) qL = ci.q_in;
-            double qRe = qR;
-            if (e == N && ci.bcr == BC_INFLOW_Q) qRe = ci.q_in;
-            edge_fluct<G, PREC>(hL, qL, zL, hR, qRe, zR, A.g, K, A.rule, Dm, Dp, bad);
+            if (e == 0) {
+                hL = ghost_h(ci.bcl, ci, hL);
+                qL = ghost_q(ci.bcl, ci, qL);
+            }
+            const double hRe = (e == N) ? ghost_h(ci.bcr, ci, hR) : hR;
+            const double qRe = (e == N) ? ghost_q(ci.bcr, ci, qR) : qR;
+            edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zR, A.g, K, A.rule, Dm, Dp, bad);
         }
         s_dm[t] = Dm[0];
         s_dm[T + t] = Dm[1];
@@ -129,14 +146,16 @@ __global__ __launch_bounds__(kMaxTile, PREC == PREC_FP64 ? DSVE_MINW_FP64 : DSVE
             const double dt = ci.cfl_dx * rcp_h(amax);
             const double r = dt * ci.inv_dx;
             const int64_t i = ci.cell0 + e;
-            // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2})   (Sec. 3, Eq. scheme)
+            // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i^n)
+            // (Sec. 3, Eq. scheme; S from the friction slope when K_s is given)
             const double hn = hR - r * (s_dm[t + 1] + Dp[0]);
-            const double qn = qR - r * (s_dm[T + t + 1] + Dp[1]);
+            double qn = qR - r * (s_dm[T + t + 1] + Dp[1]);
             const double zn = zR - r * (s_dm[2 * T + t + 1] + Dp[2]);
+            if (ci.fric > 0.0) qn = fma(dt, friction_source(hR, qR, A.g, ci.fric), qn);
             A.hn[i] = hn;
             A.qn[i] = qn;
             A.zn[i] = zn;
-            const double sp = fabs(cell_speed<PREC>(hn, qn, A.g, K, bad));
+            const double sp = fabs(cell_speed<PREC, CL>(hn, qn, A.g, K, bad));
             sp_bits = (unsigned long long)__double_as_longlong(sp);
             if (e == 0) {
                 A.t[c] += dt;
@@ -174,7 +193,7 @@ __device__ __forceinline__ int find_channel(const int64_t *off, int C, int64_t i
 // Grid-stride over cells; each workgroup keeps its running maximum for one channel at a
 // time and flushes it with one global atomic when the channel changes (cells are visited in
 // increasing order within a workgroup, so channels change monotonically).
-template <int PREC>
+template <int PREC, int CL>
 __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
 {
     __shared__ unsigned long long s_acc;
@@ -192,7 +211,7 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
         bool bad = false;
         if (active) {
             while (i >= A.off[c + 1]) ++c;
-            const double sp = fabs(cell_speed<PREC>(A.h[i], A.q[i], A.g, closure_of(A.ch[c]), bad));
+            const double sp = fabs(cell_speed<PREC, CL>(A.h[i], A.q[i], A.g, closure_of(A.ch[c]), bad));
             bits = (unsigned long long)__double_as_longlong(sp);
         }
         raise_flag(A.flags, bad);
@@ -211,14 +230,14 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
     if (threadIdx.x == 0 && reg_chan >= 0) atomicMax(&A.amax[reg_chan], reg_acc);
 }
 
-template <int G, int PREC>
+template <int G, int PREC, int CL>
 __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     if (e < A.n) {
         double Dm[3], Dp[3];
-        edge_fluct<G, PREC>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci), A.rule,
+        edge_fluct<G, PREC, CL>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci), A.rule,
                             Dm, Dp, bad);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -230,15 +249,20 @@ __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
 }
 
 __global__ __launch_bounds__(256) void k_update(const double *Dm, const double *Dp, const double *dt,
-                                                double dx, int64_t N, double *h, double *q,
-                                                double *z)
+                                                const ChanInfo *ch, double g, int64_t N, double *h,
+                                                double *q, double *z)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int64_t E = N + 1;
-    const double r = dt[0] / dx;
-    h[i] = h[i] - r * (Dm[i + 1] + Dp[i]);
-    q[i] = q[i] - r * (Dm[E + i + 1] + Dp[E + i]);
+    const double dti = dt[0];
+    const double r = dti * ch->inv_dx;
+    const double fric = ch->fric;
+    const double h0 = h[i], q0 = q[i];
+    double qn = q0 - r * (Dm[E + i + 1] + Dp[E + i]);
+    if (fric > 0.0) qn = fma(dti, friction_source(h0, q0, g, fric), qn);
+    h[i] = h0 - r * (Dm[i + 1] + Dp[i]);
+    q[i] = qn;
     z[i] = z[i] - r * (Dm[2 * E + i + 1] + Dp[2 * E + i]);
 }
 
@@ -274,93 +298,102 @@ static inline unsigned int cfl_grid(int64_t n_cells)
     return full < 2048u ? full : 2048u;
 }
 
+// Dispatch over the compile-time variants: G in [1, 5] quadrature points, closure form.
+#define DSVE_DISPATCH_G_CL(G, CL, MACRO)                                                  \
+    switch ((G) * 2 + (CL)) {                                                             \
+    case 2: MACRO(1, CL_GRASS); break;                                                    \
+    case 3: MACRO(1, CL_LAW); break;                                                      \
+    case 4: MACRO(2, CL_GRASS); break;                                                    \
+    case 5: MACRO(2, CL_LAW); break;                                                      \
+    case 6: MACRO(3, CL_GRASS); break;                                                    \
+    case 7: MACRO(3, CL_LAW); break;                                                      \
+    case 8: MACRO(4, CL_GRASS); break;                                                    \
+    case 9: MACRO(4, CL_LAW); break;                                                      \
+    case 10: MACRO(5, CL_GRASS); break;                                                   \
+    case 11: MACRO(5, CL_LAW); break;                                                     \
+    default: return hipErrorInvalidValue;                                                 \
+    }
+
 template <int PREC>
-static hipError_t launch_fluct_prec(const FluctArgs &a, int G, hipStream_t stream)
+static hipError_t launch_fluct_prec(const FluctArgs &a, int G, int cl, hipStream_t stream)
 {
     const dim3 grid(blocks_for(a.n, 256)), block(256);
-    switch (G) {
-    case 1: hipLaunchKernelGGL((k_fluct<1, PREC>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_fluct<2, PREC>), grid, block, 0, stream, a); break;
-    case 3: hipLaunchKernelGGL((k_fluct<3, PREC>), grid, block, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((k_fluct<4, PREC>), grid, block, 0, stream, a); break;
-    case 5: hipLaunchKernelGGL((k_fluct<5, PREC>), grid, block, 0, stream, a); break;
-    default: return hipErrorInvalidValue;
-    }
+#define DSVE_LAUNCH_FLUCT(GG, CC) hipLaunchKernelGGL((k_fluct<GG, PREC, CC>), grid, block, 0, stream, a)
+    DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_FLUCT)
+#undef DSVE_LAUNCH_FLUCT
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_step_prec(const StepArgs &a, int G, int tile, int grid, hipStream_t s)
+static hipError_t launch_step_prec(const StepArgs &a, int G, int cl, int tile, int grid, hipStream_t s)
 {
     const size_t lds = sizeof(double) * 3 * (size_t)tile;
-    switch (G) {
-    case 1: hipLaunchKernelGGL((k_step<1, PREC>), dim3(grid), dim3(tile), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_step<2, PREC>), dim3(grid), dim3(tile), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_step<3, PREC>), dim3(grid), dim3(tile), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<4, PREC>), dim3(grid), dim3(tile), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((k_step<5, PREC>), dim3(grid), dim3(tile), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
+#define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC>), dim3(grid), dim3(tile), lds, s, a)
+    DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_STEP)
+#undef DSVE_LAUNCH_STEP
     return hipGetLastError();
 }
 
 template <int PREC>
-static int occupancy_prec(int G, int tile)
+static hipError_t occupancy_query(int G, int cl, int tile, int &n)
 {
-    int n = 0;
     const size_t lds = sizeof(double) * 3 * (size_t)tile;
     hipError_t e = hipErrorInvalidValue;
-    switch (G) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<1, PREC>, tile, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<2, PREC>, tile, lds); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<3, PREC>, tile, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<4, PREC>, tile, lds); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<5, PREC>, tile, lds); break;
-    default: break;
-    }
+#define DSVE_OCC(GG, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<GG, PREC, CC>, tile, lds)
+    DSVE_DISPATCH_G_CL(G, cl, DSVE_OCC)
+#undef DSVE_OCC
+    return e;
+}
+
+int step_blocks_per_cu(int precision, int G, int cl, int tile)
+{
+    int n = 0;
+    const hipError_t e = precision == PREC_MIXED ? occupancy_query<PREC_MIXED>(G, cl, tile, n)
+                                                 : occupancy_query<PREC_FP64>(G, cl, tile, n);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-int step_blocks_per_cu(int precision, int G, int tile)
-{
-    return precision == PREC_MIXED ? occupancy_prec<PREC_MIXED>(G, tile)
-                                   : occupancy_prec<PREC_FP64>(G, tile);
-}
-
-hipError_t launch_step(const StepArgs &a, int precision, int G, int tile, int grid,
+hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
                        hipStream_t stream)
 {
     if (tile < 64 || tile > kMaxTile || (tile & 63) || grid < 1) return hipErrorInvalidValue;
-    if (precision == PREC_FP64) return launch_step_prec<PREC_FP64>(a, G, tile, grid, stream);
-    if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED>(a, G, tile, grid, stream);
+    if (precision == PREC_FP64) return launch_step_prec<PREC_FP64>(a, G, cl, tile, grid, stream);
+    if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED>(a, G, cl, tile, grid, stream);
     return hipErrorNotSupported;
 }
 
-hipError_t launch_cfl(const CflArgs &a, int precision, hipStream_t stream)
+hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t stream)
 {
     if (a.n_cells < 1) return hipErrorInvalidValue;
     const dim3 grid(cfl_grid(a.n_cells)), block(256);
-    if (precision == PREC_FP64) hipLaunchKernelGGL((k_cfl<PREC_FP64>), grid, block, 0, stream, a);
-    else if (precision == PREC_MIXED) hipLaunchKernelGGL((k_cfl<PREC_MIXED>), grid, block, 0, stream, a);
-    else return hipErrorNotSupported;
+    if (cl != CL_GRASS && cl != CL_LAW) return hipErrorInvalidValue;
+    if (precision == PREC_FP64) {
+        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_FP64, CL_GRASS>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_cfl<PREC_FP64, CL_LAW>), grid, block, 0, stream, a);
+    } else if (precision == PREC_MIXED) {
+        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_GRASS>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_LAW>), grid, block, 0, stream, a);
+    } else {
+        return hipErrorNotSupported;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_fluct(const FluctArgs &a, int precision, int G, hipStream_t stream)
+hipError_t launch_fluct(const FluctArgs &a, int precision, int G, int cl, hipStream_t stream)
 {
     if (a.n < 1) return hipSuccess;
-    if (precision == PREC_FP64) return launch_fluct_prec<PREC_FP64>(a, G, stream);
-    if (precision == PREC_MIXED) return launch_fluct_prec<PREC_MIXED>(a, G, stream);
+    if (precision == PREC_FP64) return launch_fluct_prec<PREC_FP64>(a, G, cl, stream);
+    if (precision == PREC_MIXED) return launch_fluct_prec<PREC_MIXED>(a, G, cl, stream);
     return hipErrorNotSupported;
 }
 
-hipError_t launch_cell_update(const double *Dm, const double *Dp, const double *dt, double,
-                              double dx, int64_t N, double *h, double *q, double *z,
-                              hipStream_t stream)
+hipError_t launch_cell_update(const double *Dm, const double *Dp, const double *dt,
+                              const ChanInfo *ch, double g, int64_t N, double *h, double *q,
+                              double *z, hipStream_t stream)
 {
     if (N < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_update, dim3(blocks_for(N, 256)), dim3(256), 0, stream, Dm, Dp, dt, dx, N,
-                       h, q, z);
+    hipLaunchKernelGGL(k_update, dim3(blocks_for(N, 256)), dim3(256), 0, stream, Dm, Dp, dt, ch, g,
+                       N, h, q, z);
     return hipGetLastError();
 }
 

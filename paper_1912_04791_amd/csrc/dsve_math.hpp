@@ -22,9 +22,17 @@
 //                           / ((mu_i - mu_j)(mu_i - mu_k)),
 //   where 2Fr - mu_j - mu_k = mu_i (the roots sum to the trace, 2Fr), and the three
 //   denominators come from the gap products (one reciprocal for all three).
+// Other closures (Sec. 2, Eqs. GrassThr, MPM, vanRijn; Sec. 5.1, Eq. Soni_qs) enter through
+// b = xi dq_s/dq, evaluated per state.  Each depends on (h, q) through the velocity u = q/h
+// (Grass-type laws) or through q^2 / h^(7/3) (laws of the Shields stress or shear velocity,
+// where s_f h and g h s_f carry that combination), and the chain rule then gives
+// xi dq_s/dh = -kappa b u with kappa = 1 or 7/6 respectively, so that
+//     k1 = 3 + Fr^2 + 3b,   k2 = Fr (18 - 2 Fr^2 + (18 - 27 kappa) b),
+//     xi (dq_s/dh dh + dq_s/dq dq) = b c (dq/c - kappa Fr dh);
+// the Grass law is kappa = 1 with b = kqg Fr^2.
 // The fluctuation (Sec. 3.1, Eq. DOTjumpN) is accumulated as
 //   S_A = sum_k w_k A(Psi_k) dW   with the explicit flux matrix (Eq. W&A_definition):
-//         A dW = [dq, c^2 ((1 - Fr^2) dh + 2Fr dq/c + dz), b c (dq/c - Fr dh)],
+//         A dW = [dq, c^2 ((1 - Fr^2) dh + 2Fr dq/c + dz), b c (dq/c - kappa Fr dh)],
 //   S_B = sum_k w_k |A(Psi_k)| dW  with |A| dW = sum_m c |mu_m| (l_m . dW) r_m   (Eqs. asbA, ExAbsA),
 //   D^- = (S_A - S_B)/2,  D^+ = (S_A + S_B)/2,
 // i.e. |A| is applied to dW as R (|Lambda| (R^-1 dW)) rather than formed as a 3x3 matrix.
@@ -109,22 +117,95 @@ __device__ __forceinline__ void trisect(double x, double &c, double &s)
 }
 
 // ---------------------------------------------------------------------------
-// Per-channel constants of the closure: kqg = 3 xi A_g g, K1 = 1 + 3 kqg, K2 = 2 + 9 kqg.
+// Per-channel constants of the closure: kqg = 3 xi A_g g, K1 = 1 + 3 kqg, K2 = 2 + 9 kqg for
+// the Grass law in closed form; the law and its constants lp0, lp1 for the general form.
 struct Closure {
     double kqg, K1, K2;
+    double lp0, lp1;
+    int law;
 };
 __device__ __forceinline__ Closure closure_of(const ChanInfo &ci)
 {
-    return Closure{ci.kqg, ci.K1, ci.K2};
+    return Closure{ci.kqg, ci.K1, ci.K2, ci.lp0, ci.lp1, ci.law};
+}
+
+__device__ __forceinline__ double m_pow(double a, double b) { return pow(a, b); }
+__device__ __forceinline__ float m_pow(float a, float b) { return powf(a, b); }
+// cube root of a > 0: FP32 estimate, then one Halley step y (y^3 + 2a) / (2y^3 + a) in FP64
+// (cubic convergence: about 2^-23 -> 2^-69 relative)
+__device__ __forceinline__ double cbrt_h(double a)
+{
+    const double y = (double)cbrtf((float)a);
+    const double y3 = y * y * y;
+    return y * fma(2.0, a, y3) * rcp_h(fma(2.0, y3, a));
+}
+__device__ __forceinline__ double m_cbrt(double a) { return cbrt_h(a); }
+__device__ __forceinline__ float m_cbrt(float a) { return cbrtf(a); }
+__device__ __forceinline__ double m_sqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float m_sqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double m_abs(double a) { return fabs(a); }
+__device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
+__device__ __forceinline__ double m_rcp(double a) { return rcp_h(a); }
+__device__ __forceinline__ float m_rcp(float a) { return 1.0f / a; }
+
+// b = xi dq_s/dq of a closure at the state (h, q), invh = 1/h (constants lp0, lp1 of the law
+// as laid out in ChanInfo).  Below a law's threshold, and at rest, b = 0.
+template <typename T>
+__device__ __forceinline__ T law_b(int law, T lp0, T lp1, T h, T q, T invh)
+{
+    const T u = q * invh;
+    const T au = m_abs(u);
+    switch (law) {
+    case LAW_GRASS:
+        return lp0 * (u * u) * invh;
+    case LAW_GRASS_THR: {
+        const T ex = au - lp1;
+        return ex > T(0) ? lp0 * (ex * ex) * invh : T(0);
+    }
+    case LAW_POWER:
+        return au > T(0) ? lp0 * m_pow(au, lp1) * invh : T(0);
+    case LAW_MPM: {
+        const T th = lp0 * (u * u) * m_rcp(m_cbrt(h));              // Shields stress
+        return th > T(0.047) ? lp1 * m_sqrt(th - T(0.047)) * th * m_rcp(m_abs(q)) : T(0);
+    }
+    default: {
+        const T tp1 = lp0 * (u * u) * m_rcp(m_cbrt(h));             // u_*^2 / u_*cr^2
+        const T tt = tp1 - T(1);
+        return tt > T(0) ? lp1 * m_pow(tt, T(1.1)) * tp1 * m_rcp(m_abs(q)) : T(0);
+    }
+    }
+}
+
+// Cubic parameters k1, k2 (Eqs. parameters, parameters_bis), b and kappa Fr at a state.
+template <int CL, typename T>
+__device__ __forceinline__ void cubic_params(const Closure &K, T h, T q, T g, T Fr, T inv_c,
+                                             T &k1, T &k2, T &b, T &kFr)
+{
+    const T Fr2 = Fr * Fr;
+    if constexpr (CL == CL_GRASS) {
+        b = T(K.kqg) * Fr2;
+        k1 = fma(Fr2, T(K.K1), T(3));
+        k2 = Fr * fma(-Fr2, T(K.K2), T(18));
+        kFr = Fr;
+    } else {
+        const T invh = g * (inv_c * inv_c);   // c^2 = g h
+        b = law_b<T>(K.law, T(K.lp0), T(K.lp1), h, q, invh);
+        const bool stress = K.law >= LAW_MPM;
+        const T kk = stress ? T(-13.5) : T(-9);   // 18 - 27 kappa
+        k1 = fma(T(3), b, fma(Fr, Fr, T(3)));
+        k2 = Fr * fma(kk, b, fma(T(-2) * Fr, Fr, T(18)));
+        kFr = stress ? T(7.0 / 6.0) * Fr : Fr;
+    }
 }
 
 // FP64 non-dimensional eigenstructure at one state.
 struct Eig64 {
-    double Fr, c, inv_c, b;
+    double Fr, c, inv_c, b, kFr;
     double mu1, mu2, mu3;
     double g21, g31, g32;   // mu_2 - mu_1, mu_3 - mu_1, mu_3 - mu_2
 };
 
+template <int CL>
 __device__ __forceinline__ void eig64(double h, double q, double g, const Closure &K, Eig64 &E,
                                       bool &bad)
 {
@@ -132,9 +213,8 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
     const double Fr = q * t;
     const double inv_c = h * t;
-    const double Fr2 = Fr * Fr;
-    const double k1 = fma(Fr2, K.K1, 3.0);
-    const double k2 = Fr * fma(-Fr2, K.K2, 18.0);
+    double k1, k2, b, kFr;
+    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
     const double r1 = rsqrt_h(k1);
     double x = (0.5 * k2) * (r1 * r1 * r1);   // k2 / sqrt(4 k1^3)
     // complex roots: arccos argument beyond 1 + tol or k1 <= 0 (NaN compares false: a NaN
@@ -149,7 +229,8 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     E.Fr = Fr;
     E.c = gh * inv_c;
     E.inv_c = inv_c;
-    E.b = K.kqg * Fr2;
+    E.b = b;
+    E.kFr = kFr;
     E.mu1 = f - m * (p + r);
     E.mu2 = f - m * (p - r);
     E.mu3 = fma(m, cs, f);
@@ -159,10 +240,11 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
 }
 
 // Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).
+template <int CL>
 __device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, bool &bad)
 {
     Eig64 E;
-    eig64(h, q, g, K, E, bad);
+    eig64<CL>(h, q, g, K, E, bad);
     return E.c * fmax(fmax(fabs(E.mu1), fabs(E.mu2)), fabs(E.mu3));
 }
 
@@ -176,7 +258,7 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
     const double base = fma(-Fr, Fr, 1.0);   // (c^2 - u^2) / c^2
     // explicit A dW (row 0 is dq)
     const double A1n = fma(base, dh, fma(2.0 * Fr, dqn, dz));
-    const double A2n = E.b * fma(-Fr, dh, dqn);
+    const double A2n = E.b * fma(-E.kFr, dh, dqn);
     // numerators of l_i . dW (non-dimensional)
     const double n1 = fma(fma(mu2, mu3, base), dh, fma(mu1, dqn, dz));
     const double n2 = fma(fma(mu3, mu1, base), dh, fma(mu2, dqn, dz));
@@ -200,7 +282,7 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
 }
 
 // DOT fluctuations of one edge, FP64 throughout.
-template <int G>
+template <int G, int CL>
 __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double hR, double qR,
                                         double zR, double g, const Closure &K, const GaussRule &rule,
                                         double Dm[3], double Dp[3], bool &bad)
@@ -211,7 +293,7 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
     for (int k = 0; k < G; ++k) {
         const double s = rule.s[k];
         Eig64 E;
-        eig64(fma(s, dh, hL), fma(s, dq, qL), g, K, E, bad);
+        eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E, bad);
         node_accumulate64(E, rule.w[k], dh, dq, dz, SA, SB);
     }
 #pragma unroll
@@ -226,22 +308,22 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 // kMixedFp64Band of +-1 (coalescing eigenvalues: Fr near +-1 with weak transport) is redone
 // in FP64 from the FP64 path state.  The jumps dW are formed in FP64 and rounded once.
 struct EigF {
-    float Fr, c, inv_c, b;
+    float Fr, c, inv_c, b, kFr;
     float mu1, mu2, mu3;
     float g21, g31, g32;
 };
 
 // Returns false when the node must be evaluated in FP64 (the FP32 argument only selects
 // the band, a width of 1e-3 far wider than FP32 rounding; it never decides a result there).
-__device__ __forceinline__ bool eigf(float h, float q, float g, float kqg, float K1, float K2, EigF &E)
+template <int CL>
+__device__ __forceinline__ bool eigf(float h, float q, float g, const Closure &K, EigF &E)
 {
     const float gh = g * h;
     const float t = __builtin_amdgcn_rsqf(gh * h * h);
     const float Fr = q * t;
     const float inv_c = h * t;
-    const float Fr2 = Fr * Fr;
-    const float k1 = fmaf(Fr2, K1, 3.0f);
-    const float k2 = Fr * fmaf(-Fr2, K2, 18.0f);
+    float k1, k2, b, kFr;
+    cubic_params<CL, float>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
     const float r1 = __builtin_amdgcn_rsqf(k1);
     float x = (0.5f * k2) * (r1 * r1 * r1);
     if (!(fabsf(x) < 1.0f - kMixedFp64Band)) return false;
@@ -253,7 +335,8 @@ __device__ __forceinline__ bool eigf(float h, float q, float g, float kqg, float
     E.Fr = Fr;
     E.c = gh * inv_c;
     E.inv_c = inv_c;
-    E.b = kqg * Fr2;
+    E.b = b;
+    E.kFr = kFr;
     E.mu1 = f - m * (p + r);
     E.mu2 = f - m * (p - r);
     E.mu3 = fmaf(m, cs, f);
@@ -271,7 +354,7 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
     const float dqn = dq * E.inv_c;
     const float base = fmaf(-Fr, Fr, 1.0f);
     const float A1n = fmaf(base, dh, fmaf(2.0f * Fr, dqn, dz));
-    const float A2n = E.b * fmaf(-Fr, dh, dqn);
+    const float A2n = E.b * fmaf(-E.kFr, dh, dqn);
     const float n1 = fmaf(fmaf(mu2, mu3, base), dh, fmaf(mu1, dqn, dz));
     const float n2 = fmaf(fmaf(mu3, mu1, base), dh, fmaf(mu2, dqn, dz));
     const float n3 = fmaf(fmaf(mu1, mu2, base), dh, fmaf(mu3, dqn, dz));
@@ -292,7 +375,7 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
     SB[2] = fmaf(c, B2, SB[2]);
 }
 
-template <int G>
+template <int G, int CL>
 __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, double hR, double qR,
                                             double zR, double g, const Closure &K,
                                             const GaussRule &rule, double Dm[3], double Dp[3],
@@ -301,19 +384,19 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     const float dhf = (float)dh, dqf = (float)dq, dzf = (float)dz;
     const float hLf = (float)hL, qLf = (float)qL;
-    const float gf = (float)g, kqgf = (float)K.kqg, K1f = (float)K.K1, K2f = (float)K.K2;
+    const float gf = (float)g;
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
     double SA64[3] = {0.0, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const float sf = (float)rule.s[k];
         EigF E;
-        if (eigf(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, kqgf, K1f, K2f, E)) {
+        if (eigf<CL>(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, K, E)) {
             node_accumulatef(E, (float)rule.w[k], dhf, dqf, dzf, SA, SB);
         } else {
             const double s = rule.s[k];
             Eig64 E64;
-            eig64(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, bad);
+            eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, bad);
             node_accumulate64(E64, rule.w[k], dh, dq, dz, SA64, SB64);
         }
     }
@@ -325,13 +408,21 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     }
 }
 
+template <int CL>
 __device__ __forceinline__ double speed_mixed(double h, double q, double g, const Closure &K,
                                               bool &bad)
 {
     EigF E;
-    if (eigf((float)h, (float)q, (float)g, (float)K.kqg, (float)K.K1, (float)K.K2, E))
+    if (eigf<CL>((float)h, (float)q, (float)g, K, E))
         return (double)(E.c * fmaxf(fmaxf(fabsf(E.mu1), fabsf(E.mu2)), fabsf(E.mu3)));
-    return speed64(h, q, g, K, bad);
+    return speed64<CL>(h, q, g, K, bad);
+}
+
+// Friction source of the momentum equation (Sec. 2): -g h s_f with
+// s_f = q |q| / (K_s^2 h^(10/3)), fric = 1 / K_s^2; evaluated in FP64 at the old cell state.
+__device__ __forceinline__ double friction_source(double h, double q, double g, double fric)
+{
+    return -g * (q * fabs(q)) * fric * rcp_h(h * h * cbrt_h(h));
 }
 
 }  // namespace dsve

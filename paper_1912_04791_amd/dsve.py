@@ -25,7 +25,13 @@ E_UNSUPPORTED = -5
 BC_TRANSMISSIVE = 0
 BC_PERIODIC = 1
 BC_INFLOW_Q = 2
+BC_FIXED_DEPTH = 3
+BC_INFLOW_QH = 4
 LAW_GRASS = 0
+LAW_GRASS_THR = 1
+LAW_POWER = 2
+LAW_MPM = 3
+LAW_VANRIJN = 4
 FP64 = 0
 MIXED = 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
@@ -51,6 +57,25 @@ class Params(ctypes.Structure):
         ("bc_right", ctypes.c_int),
         ("q_in", ctypes.c_double),
         ("precision", ctypes.c_int),
+        ("h_in", ctypes.c_double),
+        ("h_out", ctypes.c_double),
+        ("ks", ctypes.c_double),
+    ]
+
+
+class Channel(ctypes.Structure):
+    """Mirror of ``dsve_channel``."""
+    _fields_ = [
+        ("A_g", ctypes.c_double),
+        ("porosity", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("q_in", ctypes.c_double),
+        ("h_in", ctypes.c_double),
+        ("h_out", ctypes.c_double),
+        ("ks", ctypes.c_double),
+        ("law_extra", ctypes.c_double * 4),
+        ("bc_left", ctypes.c_int),
+        ("bc_right", ctypes.c_int),
     ]
 
 
@@ -61,7 +86,7 @@ _ctxp = ctypes.c_void_p
 lib = ctypes.CDLL(LIB_PATH)
 lib.dsve_abi_version.restype = ctypes.c_int
 lib.dsve_init.argtypes = [ctypes.POINTER(_ctxp), ctypes.POINTER(Params), _i64, _vp]
-lib.dsve_batch_init.argtypes = [ctypes.POINTER(_ctxp), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+lib.dsve_batch_init.argtypes = [ctypes.POINTER(_ctxp), _i64, _vp, ctypes.POINTER(Channel),
                                 ctypes.POINTER(Params), _vp]
 lib.dsve_destroy.argtypes = [_ctxp]
 lib.dot_edge_fluct.argtypes = [_ctxp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]
@@ -79,7 +104,7 @@ lib.dsve_get_launch.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POIN
 lib.dsve_autotune.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_char_p]
 lib.dsve_device_cus.argtypes = [_ctxp]
 lib.dsve_device_cus.restype = ctypes.c_int
-assert lib.dsve_abi_version() == 1, "libdsve ABI version mismatch"
+assert lib.dsve_abi_version() == 2, "libdsve ABI version mismatch"
 
 ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destroy",
                 "dot_edge_fluct", "cell_update", "cfl_reduce", "adot_step", "adot_step_batched",
@@ -111,14 +136,16 @@ def _stream_handle(stream) -> int:
 
 def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
                 bc_left=BC_TRANSMISSIVE, bc_right=BC_TRANSMISSIVE, q_in=0.0,
-                precision="fp64") -> Params:
+                precision="fp64", law=LAW_GRASS, law_extra=(), h_in=0.0, h_out=0.0,
+                ks=0.0) -> Params:
     p = Params()
     p.g = g
     p.porosity = porosity
-    p.law = LAW_GRASS
+    p.law = int(law)
     p.A_g = A_g
+    ex = list(law_extra) + [0.0] * (4 - len(law_extra))
     for k in range(4):
-        p.law_extra[k] = 0.0
+        p.law_extra[k] = float(ex[k])
     p.n_gauss = n_gauss
     p.cfl = cfl
     p.dx = dx
@@ -126,7 +153,33 @@ def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
     p.bc_right = bc_right
     p.q_in = q_in
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.h_in = h_in
+    p.h_out = h_out
+    p.ks = ks
     return p
+
+
+def make_channels(A_g, porosity, dx, bc_left, bc_right, q_in=None, h_in=None, h_out=None,
+                  ks=None, law_extra=None):
+    """A ``dsve_channel`` array from per-channel arrays (missing ones are zero)."""
+    C = len(A_g)
+    z = np.zeros(C)
+    cols = [np.asarray(a if a is not None else z, dtype=np.float64)
+            for a in (A_g, porosity, dx, q_in, h_in, h_out, ks)]
+    ex = np.zeros((C, 4)) if law_extra is None else np.asarray(law_extra, dtype=np.float64).reshape(C, 4)
+    bcl = np.asarray(bc_left, dtype=np.int32)
+    bcr = np.asarray(bc_right, dtype=np.int32)
+    for a in (*cols, bcl, bcr):
+        assert a.shape[0] == C
+    arr = (Channel * C)()
+    for c in range(C):
+        ch = arr[c]
+        ch.A_g, ch.porosity, ch.dx, ch.q_in, ch.h_in, ch.h_out, ch.ks = (float(a[c]) for a in cols)
+        for k in range(4):
+            ch.law_extra[k] = float(ex[c, k])
+        ch.bc_left = int(bcl[c])
+        ch.bc_right = int(bcr[c])
+    return arr
 
 
 class Context:
@@ -150,20 +203,15 @@ class Context:
 
     @classmethod
     def batch(cls, offsets, A_g, porosity, dx, bc_left, bc_right, q_in=None, stream=None,
-              **common) -> "Context":
+              h_in=None, h_out=None, ks=None, law_extra=None, **common) -> "Context":
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         C = off.size - 1
-        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (A_g, porosity, dx)]
-        bcl = np.ascontiguousarray(bc_left, dtype=np.int32)
-        bcr = np.ascontiguousarray(bc_right, dtype=np.int32)
-        qin = np.ascontiguousarray(np.zeros(C) if q_in is None else q_in, dtype=np.float64)
-        for a in (*arrs, bcl, bcr, qin):
-            assert a.size == C
+        chans = make_channels(A_g, porosity, dx, bc_left, bc_right, q_in, h_in, h_out, ks,
+                              law_extra)
+        assert len(chans) == C
         p = make_params(**common)
         h = _ctxp()
-        st = lib.dsve_batch_init(ctypes.byref(h), C, off.ctypes.data, arrs[0].ctypes.data,
-                                 arrs[1].ctypes.data, arrs[2].ctypes.data, bcl.ctypes.data,
-                                 bcr.ctypes.data, qin.ctypes.data, ctypes.byref(p),
+        st = lib.dsve_batch_init(ctypes.byref(h), C, off.ctypes.data, chans, ctypes.byref(p),
                                  _stream_handle(stream))
         if st != OK:
             raise DsveError(st, "dsve_batch_init failed")
@@ -178,9 +226,13 @@ class Context:
                               A_g=float(wl.Ag[0]), n_gauss=wl.n_gauss, cfl=wl.cfl,
                               dx=float(wl.dx[0]), bc_left=int(wl.bc_left[0]),
                               bc_right=int(wl.bc_right[0]), q_in=float(wl.q_in[0]),
-                              precision=prec)
+                              precision=prec, law=wl.law, law_extra=tuple(wl.law_par[0]),
+                              h_in=float(wl.h_in[0]), h_out=float(wl.h_out[0]),
+                              ks=float(wl.ks[0]))
         return cls.batch(wl.offsets, wl.Ag, wl.porosity, wl.dx, wl.bc_left, wl.bc_right, wl.q_in,
-                         stream=stream, g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl, precision=prec)
+                         stream=stream, h_in=wl.h_in, h_out=wl.h_out, ks=wl.ks,
+                         law_extra=wl.law_par, g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl,
+                         precision=prec, law=wl.law)
 
     # -- helpers ----------------------------------------------------------
     def _check(self, st: int, what: str):

@@ -29,6 +29,27 @@ Workloads (all synthetic; the paper's own test data are not used):
   L_c = N_c * 1000 / 2^20 with modes |m| <= 8, half Riemann channels built with
   the ``c4`` recipe; A_g and porosity drawn per channel as in ``c4``; 5000 steps.
 
+Workloads of the other closures, the friction source and the experiment boundary conditions,
+shaped like the paper's laboratory cases (their measured data are not used):
+
+* ``soni`` -- aggradation by sediment overfeeding (Sec. 5.1): flume of 30 m, uniform flow
+  h0 = 0.05 m, q0 = 0.02 m^2/s on the bed slope s0 = 3.56e-3 (z = 1.2 - s0 x), power law
+  q_s = 1.45e-3 u^5, porosity 0.4, K_s = 49.4; upstream inflow-(q, h) with q0 and
+  h_in = 5^(-1/5) h0 (the depth at which the power law carries five times the equilibrium
+  solid discharge at q0), downstream fixed depth h0.  The batched form draws per channel
+  N_c in {512..4096}, q0 ~ U[0.015, 0.025], s0 ~ U[3e-3, 4e-3], K_s ~ U[45, 55], an
+  overfeeding factor F ~ U[2, 5] (h_in = F^(-1/5) h0) and h0 = (q0^2 / (K_s^2 s0))^(3/10),
+  the uniform-flow depth of the friction law.
+* ``bellal_<law>`` -- sediment bore in a steep flume (Sec. 5.2): 6.9 m, s0 = 3.02e-2,
+  q0 = 0.024 m^2/s (12 l/s over 0.5 m), d50 = 1.65 mm, porosity 0.42, K_s = 62, S_g = 2.6,
+  nu = 1e-6, theta_cr = 0.03; start from the uniform flow h0 = (q0^2 / (K_s^2 s0))^(3/10)
+  (supercritical) and raise the downstream depth to 0.2093 m (fixed depth) at t = 0, with the
+  upstream discharges held at their equilibrium values (inflow-(q, h) with h0).  Laws:
+  ``mpm`` (Meyer-Peter & Mueller), ``vanrijn`` (Van Rijn), ``thr`` (Grass with threshold,
+  A_g = 0.0024, u_cr = 0.3).  The batched form draws per channel N_c in {512..4096},
+  q0 ~ U[0.02, 0.028], s0 ~ U[0.025, 0.035], d50 ~ U[1.2, 2.0] mm, K_s ~ U[55, 70] and the
+  downstream depth ~ U[0.15, 0.25].
+
 Every generator takes scale parameters so the same recipe can be built at a
 size the oracle finishes in seconds.
 """
@@ -43,6 +64,18 @@ G_ACC = 9.81
 BC_TRANSMISSIVE = 0
 BC_PERIODIC = 1
 BC_INFLOW_Q = 2
+BC_FIXED_DEPTH = 3
+BC_INFLOW_QH = 4
+
+LAW_GRASS = 0
+LAW_GRASS_THR = 1
+LAW_POWER = 2
+LAW_MPM = 3
+LAW_VANRIJN = 4
+
+# per-channel array fields of a Workload, in the order channel()/subset() copy them
+PER_CHANNEL = ("dx", "Ag", "porosity", "bc_left", "bc_right", "q_in", "h_in", "h_out", "ks",
+               "law_par")
 
 
 @dataclass
@@ -66,6 +99,20 @@ class Workload:
     precision: str = "fp64"
     seed: int | None = None
     meta: dict = field(default_factory=dict)
+    law: int = LAW_GRASS         # closure, common to all channels
+    law_par: np.ndarray | None = None   # float64 [C, 4] parameters of the law per channel
+    ks: np.ndarray | None = None        # float64 [C] Strickler coefficient (0: no friction)
+    h_in: np.ndarray | None = None      # float64 [C] depth of an inflow-(q, h) boundary
+    h_out: np.ndarray | None = None     # float64 [C] depth of a fixed-depth boundary
+
+    def __post_init__(self):
+        C = self.offsets.size - 1
+        if self.law_par is None:
+            self.law_par = np.zeros((C, 4))
+        self.law_par = np.ascontiguousarray(np.asarray(self.law_par, dtype=np.float64).reshape(C, 4))
+        for f in ("ks", "h_in", "h_out"):
+            v = getattr(self, f)
+            setattr(self, f, np.zeros(C) if v is None else np.asarray(v, dtype=np.float64).reshape(C))
 
     @property
     def n_channels(self) -> int:
@@ -86,31 +133,22 @@ class Workload:
 
     def channel(self, c: int) -> "Workload":
         """The single-channel workload of channel c (copies of its arrays)."""
-        lo, hi = int(self.offsets[c]), int(self.offsets[c + 1])
-        return Workload(
-            name=f"{self.name}[{c}]", h=self.h[lo:hi].copy(), q=self.q[lo:hi].copy(),
-            z=self.z[lo:hi].copy(), offsets=np.array([0, hi - lo], dtype=np.int64),
-            dx=self.dx[c:c + 1].copy(), Ag=self.Ag[c:c + 1].copy(),
-            porosity=self.porosity[c:c + 1].copy(), bc_left=self.bc_left[c:c + 1].copy(),
-            bc_right=self.bc_right[c:c + 1].copy(), q_in=self.q_in[c:c + 1].copy(),
-            steps=self.steps, g=self.g, cfl=self.cfl, n_gauss=self.n_gauss,
-            precision=self.precision, seed=self.seed, meta=dict(self.meta))
+        return self.subset([c], name=f"{self.name}[{c}]")
 
-    def subset(self, channels) -> "Workload":
+    def subset(self, channels, name: str | None = None) -> "Workload":
         """A workload made of the listed channels (copies)."""
         channels = np.asarray(channels, dtype=np.int64)
         parts = [(int(self.offsets[c]), int(self.offsets[c + 1])) for c in channels]
         lens = np.array([hi - lo for lo, hi in parts], dtype=np.int64)
         off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
         cat = lambda a: np.concatenate([a[lo:hi] for lo, hi in parts]) if parts else a[:0]
+        per = {f: getattr(self, f)[channels].copy() for f in PER_CHANNEL}
+        meta = dict(self.meta) if channels.size == 1 else dict(self.meta, subset=channels.tolist()[:16])
         return Workload(
-            name=f"{self.name}[subset {channels.size}]", h=cat(self.h), q=cat(self.q),
-            z=cat(self.z), offsets=off, dx=self.dx[channels].copy(), Ag=self.Ag[channels].copy(),
-            porosity=self.porosity[channels].copy(), bc_left=self.bc_left[channels].copy(),
-            bc_right=self.bc_right[channels].copy(), q_in=self.q_in[channels].copy(),
-            steps=self.steps, g=self.g, cfl=self.cfl, n_gauss=self.n_gauss,
-            precision=self.precision, seed=self.seed,
-            meta=dict(self.meta, subset=channels.tolist()[:16]))
+            name=name or f"{self.name}[subset {channels.size}]", h=cat(self.h), q=cat(self.q),
+            z=cat(self.z), offsets=off, steps=self.steps, g=self.g, cfl=self.cfl,
+            n_gauss=self.n_gauss, precision=self.precision, seed=self.seed, meta=meta,
+            law=self.law, **per)
 
 
 def _single(name, h, q, z, dx, Ag, porosity, bc_l, bc_r, q_in, steps, **kw) -> Workload:
@@ -233,7 +271,7 @@ def riemann_state(rng: np.random.Generator, n: int):
     return h, h * u, z
 
 
-def _assemble(name, parts, dx, Ag, por, bcl, bcr, steps, seed, **kw) -> Workload:
+def _assemble(name, parts, dx, Ag, por, bcl, bcr, steps, seed, q_in=None, **kw) -> Workload:
     lens = np.array([p[0].size for p in parts], dtype=np.int64)
     off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     C = lens.size
@@ -242,7 +280,9 @@ def _assemble(name, parts, dx, Ag, por, bcl, bcr, steps, seed, **kw) -> Workload
         q=np.concatenate([p[1] for p in parts]), z=np.concatenate([p[2] for p in parts]),
         offsets=off, dx=np.asarray(dx, dtype=np.float64), Ag=np.asarray(Ag, dtype=np.float64),
         porosity=np.asarray(por, dtype=np.float64), bc_left=np.asarray(bcl, dtype=np.int32),
-        bc_right=np.asarray(bcr, dtype=np.int32), q_in=np.zeros(C), steps=steps, seed=seed, **kw)
+        bc_right=np.asarray(bcr, dtype=np.int32),
+        q_in=np.zeros(C) if q_in is None else np.asarray(q_in, dtype=np.float64), steps=steps,
+        seed=seed, **kw)
 
 
 def make_c4(n_channels: int = 4096, len_lo: int = 256, len_hi: int = 65536, steps: int = 500,
@@ -300,6 +340,88 @@ def make_c5(n_channels: int = 65536, len_lo: int = 512, len_hi: int = 4096, step
                      meta={"kind": kind})
 
 
+# ---------------------------------------------------------------------------
+def uniform_flow_depth(q: np.ndarray, ks: np.ndarray, slope: np.ndarray) -> np.ndarray:
+    """Depth at which the friction slope q^2 / (K_s^2 h^(10/3)) equals the bed slope."""
+    return (np.asarray(q) ** 2 / (np.asarray(ks) ** 2 * np.asarray(slope))) ** 0.3
+
+
+def _sloped_channel(n: int, length: float, h0: float, q0: float, slope: float, z0: float):
+    x = cell_centres(n, length)
+    return np.full(n, h0), np.full(n, q0), z0 - slope * x
+
+
+def make_soni(n_channels: int = 8192, len_lo: int = 512, len_hi: int = 4096, steps: int = 2000,
+              seed: int = 21, n_cells: int | None = None) -> Workload:
+    """Sec. 5.1-shaped aggradation runs (power law, friction, inflow-(q, h), fixed depth).
+
+    With n_channels = 1 and n_cells given: the paper's single flume with its stated values."""
+    L, beta, alpha, por = 30.0, 5.0, 1.45e-3, 0.4
+    if n_channels == 1:
+        n = n_cells or 100
+        h0, q0, s0, ks, feed = 0.05, 0.02, 3.56e-3, 49.4, 5.0
+        lens = np.array([n])
+        q0v, s0v, ksv, feedv, h0v = [np.array([v]) for v in (q0, s0, ks, feed, h0)]
+    else:
+        ss = np.random.SeedSequence(seed)
+        top = np.random.default_rng(ss.spawn(1)[0])
+        lens = top.integers(len_lo, len_hi + 1, n_channels).astype(np.int64)
+        q0v = top.uniform(0.015, 0.025, n_channels)
+        s0v = top.uniform(3e-3, 4e-3, n_channels)
+        ksv = top.uniform(45.0, 55.0, n_channels)
+        feedv = top.uniform(2.0, 5.0, n_channels)
+        h0v = uniform_flow_depth(q0v, ksv, s0v)
+    C = lens.size
+    parts = [_sloped_channel(int(lens[c]), L, h0v[c], q0v[c], s0v[c], 1.2) for c in range(C)]
+    par = np.zeros((C, 4))
+    par[:, 0] = beta
+    return _assemble("soni", parts, L / lens, np.full(C, alpha), np.full(C, por),
+                     np.full(C, BC_INFLOW_QH), np.full(C, BC_FIXED_DEPTH), steps, seed, q_in=q0v,
+                     law=LAW_POWER, law_par=par, ks=ksv, h_in=h0v * feedv ** (-1.0 / beta),
+                     h_out=h0v)
+
+
+BELLAL_LAWS = {"mpm": LAW_MPM, "vanrijn": LAW_VANRIJN, "thr": LAW_GRASS_THR}
+
+
+def make_bellal(law: str = "mpm", n_channels: int = 8192, len_lo: int = 512, len_hi: int = 4096,
+                steps: int = 2000, seed: int = 22, n_cells: int | None = None) -> Workload:
+    """Sec. 5.2-shaped sediment-bore runs with one of the three closures of that section.
+
+    With n_channels = 1 and n_cells given: the paper's single flume with its stated values."""
+    L, por, Sg, nu, theta_cr = 6.9, 0.42, 2.6, 1e-6, 0.03
+    code = BELLAL_LAWS[law]
+    if n_channels == 1:
+        lens = np.array([n_cells or 200])
+        q0v, s0v, d50v, ksv, houtv = [np.array([v]) for v in (0.024, 0.0302, 1.65e-3, 62.0, 0.2093)]
+    else:
+        ss = np.random.SeedSequence(seed)
+        top = np.random.default_rng(ss.spawn(1)[0])
+        lens = top.integers(len_lo, len_hi + 1, n_channels).astype(np.int64)
+        q0v = top.uniform(0.02, 0.028, n_channels)
+        s0v = top.uniform(0.025, 0.035, n_channels)
+        d50v = top.uniform(1.2e-3, 2.0e-3, n_channels)
+        ksv = top.uniform(55.0, 70.0, n_channels)
+        houtv = top.uniform(0.15, 0.25, n_channels)
+    C = lens.size
+    h0v = uniform_flow_depth(q0v, ksv, s0v)
+    parts = [_sloped_channel(int(lens[c]), L, h0v[c], q0v[c], s0v[c], s0v[c] * L) for c in range(C)]
+    par = np.zeros((C, 4))
+    Ag = np.zeros(C)
+    if code == LAW_GRASS_THR:
+        Ag[:] = 0.0024
+        par[:, 0] = 0.3
+    else:
+        par[:, 0] = d50v
+        par[:, 1] = Sg
+        if code == LAW_VANRIJN:
+            par[:, 2] = nu
+            par[:, 3] = theta_cr
+    return _assemble(f"bellal_{law}", parts, L / lens, Ag, np.full(C, por),
+                     np.full(C, BC_INFLOW_QH), np.full(C, BC_FIXED_DEPTH), steps, seed, q_in=q0v,
+                     law=code, law_par=par, ks=ksv, h_in=h0v, h_out=houtv)
+
+
 def make_lake_at_rest(n_cells: int = 400, length: float = 10.0, level: float = 1.0,
                       Ag: float = 0.01, steps: int = 200, seed: int = 7) -> Workload:
     """Still water over a rough bed: u = 0, h + z = level (periodic)."""
@@ -324,7 +446,10 @@ def make_random_edges(n: int, seed: int = 11, h_range=(0.05, 5.0), u_range=(-3.0
     return (hL, hL * uL, zL), (hR, hR * uR, zR)
 
 
-MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
+MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5,
+          "soni": make_soni, "bellal_mpm": lambda **kw: make_bellal("mpm", **kw),
+          "bellal_vanrijn": lambda **kw: make_bellal("vanrijn", **kw),
+          "bellal_thr": lambda **kw: make_bellal("thr", **kw)}
 
 DESCRIPTIONS = {
     "c1": "c1: Riemann problem on [0, 10] m, N=250, A_g=0.01, porosity 0.4, G=3, CFL 0.9, "
@@ -337,4 +462,12 @@ DESCRIPTIONS = {
           "Riemann states, per-channel A_g and porosity, G=3, CFL 0.9, 500 steps",
     "c5": "c5: 65536 channels, lengths uniform in [512, 4096] (1.5e8 cells), half smooth "
           "periodic, half Riemann, per-channel A_g and porosity, G=3, CFL 0.9, 5000 steps",
+    "soni": "soni: 8192 overfed 30 m flumes, lengths uniform in [512, 4096], power law "
+            "1.45e-3 u^5, Strickler friction, inflow-(q, h) and fixed-depth ends, per-channel "
+            "q0, slope, K_s and feed, G=3, CFL 0.9, 2000 steps",
+    "bellal_mpm": "bellal_mpm: 8192 steep 6.9 m flumes with a downstream depth step, lengths "
+                  "uniform in [512, 4096], Meyer-Peter & Mueller, Strickler friction, per-channel "
+                  "q0, slope, d50, K_s, outlet depth, G=3, CFL 0.9, 2000 steps",
+    "bellal_vanrijn": "bellal_vanrijn: as bellal_mpm with the Van Rijn closure",
+    "bellal_thr": "bellal_thr: as bellal_mpm with Grass with threshold (A_g 0.0024, u_cr 0.3)",
 }

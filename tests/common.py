@@ -9,7 +9,9 @@ def spec_of(wl: inputs.Workload, c: int = 0) -> "oracle.ChannelSpec":
     return oracle.ChannelSpec(n_cells=int(wl.lengths()[c]), dx=float(wl.dx[c]), Ag=float(wl.Ag[c]),
                               porosity=float(wl.porosity[c]), g=wl.g, n_gauss=wl.n_gauss,
                               cfl=wl.cfl, bc_left=int(wl.bc_left[c]), bc_right=int(wl.bc_right[c]),
-                              q_in=float(wl.q_in[c]))
+                              q_in=float(wl.q_in[c]), h_out=float(wl.h_out[c]),
+                              h_in=float(wl.h_in[c]), law=int(wl.law),
+                              par=tuple(float(v) for v in wl.law_par[c]), ks=float(wl.ks[c]))
 
 
 def oracle_run(wl: inputs.Workload, steps: int | None = None, nthreads: int | None = None):

@@ -102,6 +102,15 @@ def checks(lib):
         out["fixed_depth"] = bool(np.array_equal(hr, hs) and np.array_equal(qr, qs2))
     except oracle.OracleError:
         out["fixed_depth"] = False
+    spec = oracle.ChannelSpec(n_cells=32, dx=0.1, Ag=0.01, porosity=0.4,
+                              bc_left=oracle.BC_INFLOW_QH, q_in=0.33, h_in=0.95)
+    try:
+        hr, qr, zr, _ = oracle.run(spec, hb, qb, zb, 1, nthreads=2, lib=lib)
+        hs, qs2, zs = oracle.step(hb, qb, zb, [0.95, 0.33, zb[0]], [hb[-1], qb[-1], zb[-1]], G, 1 / 0.6,
+                                  0.01, 3, 0.9 * 0.1 / am, 0.1, lib=lib)
+        out["inflow_qh"] = bool(np.array_equal(hr, hs) and np.array_equal(qr, qs2))
+    except oracle.OracleError:
+        out["inflow_qh"] = False
 
     for name, wl, periodic in (("scheme_c1", inputs.make_c1(n_cells=120, steps=25), False),
                                ("scheme_periodic", inputs.make_c2(n_cells=256, steps=25), True)):

@@ -198,6 +198,44 @@ def test_fixed_depth_ghost(orc):
     assert abs(h1[-1] - h[-1]) > 1e-6   # the imposed depth entered
 
 
+def test_inflow_qh_ghost(orc):
+    # inflow-(q, h) on the left (ghost = (h_in, q_in, z_0)), fixed depth on the right
+    n, dx = 48, 0.1
+    rng = np.random.default_rng(7)
+    h = 0.05 + 0.002 * rng.uniform(-1, 1, n)
+    q = 0.02 + 0.001 * rng.uniform(-1, 1, n)
+    z = 1.2 - 0.00356 * (np.arange(n) + 0.5) * dx
+    law, par = orc.LAW_POWER, (5.0,)
+    spec = orc.ChannelSpec(n_cells=n, dx=dx, Ag=1.45e-3, porosity=0.4, law=law, par=par, ks=49.4,
+                           bc_left=orc.BC_INFLOW_QH, bc_right=orc.BC_FIXED_DEPTH, q_in=0.02,
+                           h_in=0.038, h_out=0.05)
+    h1, q1, z1, t = orc.run(spec, h, q, z, 1)
+    xi = 1 / 0.6
+    amax = orc.cfl_amax(h, q, z, G, xi, 1.45e-3, law=law, par=par, ks=49.4)
+    hs, qs, zs = orc.step(h, q, z, [0.038, 0.02, z[0]], [0.05, q[-1], z[-1]], G, xi, 1.45e-3, 3,
+                          0.9 * dx / amax, dx, law=law, par=par, ks=49.4)
+    assert np.array_equal(h1, hs) and np.array_equal(q1, qs) and np.array_equal(z1, zs)
+
+
+def test_sediment_overfeeding_aggrades_the_inflow_reach(orc):
+    # uniform flow in equilibrium (friction slope = bed slope), then a solid discharge of five
+    # times the equilibrium one fed upstream through the inflow depth: a wedge of deposit forms,
+    # thickest at the inflow and thinning downstream (Sec. 5.1 set-up)
+    n, dx, Ag, beta, q0, h0 = 100, 0.3, 1.45e-3, 5.0, 0.02, 0.05
+    x = (np.arange(n) + 0.5) * dx
+    z = 1.2 - 0.00356 * x
+    u_in = (5.0 * (q0 / h0) ** beta) ** (1.0 / beta)
+    spec = orc.ChannelSpec(n_cells=n, dx=dx, Ag=Ag, porosity=0.4, law=orc.LAW_POWER, par=(beta,),
+                           ks=49.4, bc_left=orc.BC_INFLOW_QH, bc_right=orc.BC_FIXED_DEPTH,
+                           q_in=q0, h_in=q0 / u_in, h_out=h0)
+    h1, q1, z1, t = orc.run(spec, np.full(n, h0), np.full(n, q0), z, 1500)
+    dz = z1 - z
+    assert dz[0] > 1e-3
+    assert np.all(np.diff(dz[:12]) < 0)            # the deposit thins downstream ...
+    assert np.max(np.abs(dz[25:60])) < 1e-2 * dz[0]  # ... and has not reached mid-channel
+    assert np.all(np.isfinite(h1)) and h1.min() > 0
+
+
 def test_closures_need_a_strickler_coefficient(orc):
     spec = orc.ChannelSpec(n_cells=8, dx=0.1, Ag=0.0, law=orc.LAW_MPM, par=(3e-4, 2.6), ks=0.0)
     with pytest.raises(orc.OracleError) as ei:
