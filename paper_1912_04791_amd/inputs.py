@@ -48,7 +48,9 @@ shaped like the paper's laboratory cases (their measured data are not used):
   ``mpm`` (Meyer-Peter & Mueller), ``vanrijn`` (Van Rijn), ``thr`` (Grass with threshold,
   A_g = 0.0024, u_cr = 0.3).  The batched form draws per channel N_c in {512..4096},
   q0 ~ U[0.02, 0.028], s0 ~ U[0.025, 0.035], d50 ~ U[1.2, 2.0] mm, K_s ~ U[55, 70] and the
-  downstream depth ~ U[0.15, 0.25].
+  downstream depth ~ U[0.07, 0.11] m: 1.2 to 2 times the depth conjugate to the inflow, so
+  that, as in the experiment, a bore advances slowly upstream (a 0.21 m step over a 2.6 cm
+  supercritical flow instead floods the flume backwards within seconds, with q changing sign).
 
 Every generator takes scale parameters so the same recipe can be built at a
 size the oracle finishes in seconds.
@@ -402,7 +404,7 @@ def make_bellal(law: str = "mpm", n_channels: int = 8192, len_lo: int = 512, len
         s0v = top.uniform(0.025, 0.035, n_channels)
         d50v = top.uniform(1.2e-3, 2.0e-3, n_channels)
         ksv = top.uniform(55.0, 70.0, n_channels)
-        houtv = top.uniform(0.15, 0.25, n_channels)
+        houtv = top.uniform(0.07, 0.11, n_channels)
     C = lens.size
     h0v = uniform_flow_depth(q0v, ksv, s0v)
     parts = [_sloped_channel(int(lens[c]), L, h0v[c], q0v[c], s0v[c], s0v[c] * L) for c in range(C)]
@@ -467,7 +469,7 @@ DESCRIPTIONS = {
             "q0, slope, K_s and feed, G=3, CFL 0.9, 2000 steps",
     "bellal_mpm": "bellal_mpm: 8192 steep 6.9 m flumes with a downstream depth step, lengths "
                   "uniform in [512, 4096], Meyer-Peter & Mueller, Strickler friction, per-channel "
-                  "q0, slope, d50, K_s, outlet depth, G=3, CFL 0.9, 2000 steps",
+                  "q0, slope, d50, K_s, outlet depth 0.07-0.11 m, G=3, CFL 0.9, 2000 steps",
     "bellal_vanrijn": "bellal_vanrijn: as bellal_mpm with the Van Rijn closure",
     "bellal_thr": "bellal_thr: as bellal_mpm with Grass with threshold (A_g 0.0024, u_cr 0.3)",
 }
