@@ -156,7 +156,9 @@ def cpu_baseline(wl, budget_s: float = 12.0):
                                 bc_right=int(sample.bc_right[c]), q_in=float(sample.q_in[c]),
                                 h_in=float(sample.h_in[c]), h_out=float(sample.h_out[c]),
                                 law=int(sample.law), par=tuple(float(v) for v in sample.law_par[c]),
-                                ks=float(sample.ks[c]))
+                                ks=float(sample.ks[c]),
+                                dir_left=tuple(float(v) for v in sample.dir_left[c]),
+                                dir_right=tuple(float(v) for v in sample.dir_right[c]))
              for c in range(sample.n_channels)]
 
     def run(n):

@@ -63,9 +63,13 @@ typedef enum {
  *   INFLOW_Q      (h_a, q_in, z_a): imposed discharge
  *   FIXED_DEPTH   (h_out, q_a, z_a): imposed depth, e.g. a downstream control (Sec. 5.1, 5.2)
  *   INFLOW_QH     (h_in, q_in, z_a): imposed discharge and depth; an imposed solid discharge
- *                 enters as the depth at which the closure gives it for q_in (Sec. 5.1) */
+ *                 enters as the depth at which the closure gives it for q_in (Sec. 5.1)
+ *   DIRICHLET     (h_d, q_d, z_d + t dz/dt) from dir_left / dir_right = {h_d, q_d, z_d, dz/dt},
+ *                 t the channel's clock at the start of the step: a given ghost state whose bed
+ *                 moves at a constant rate (the ghost cells of the analytical solution of
+ *                 Sec. 4.2, Eq. berthon, whose bed falls linearly in time) */
 enum { DSVE_BC_TRANSMISSIVE = 0, DSVE_BC_PERIODIC = 1, DSVE_BC_INFLOW_Q = 2,
-       DSVE_BC_FIXED_DEPTH = 3, DSVE_BC_INFLOW_QH = 4 };
+       DSVE_BC_FIXED_DEPTH = 3, DSVE_BC_INFLOW_QH = 4, DSVE_BC_DIRICHLET = 5 };
 
 /* Bed-load closures q_s(h, q), u = q/h, acting in the direction of the flow.  law_extra[]
  * holds the law's parameters; entries a law does not use must be zero.
@@ -99,6 +103,7 @@ enum { DSVE_FP64 = 0, DSVE_MIXED = 1 };
  *   q_in       unit discharge imposed by INFLOW_Q and INFLOW_QH
  *   h_in       depth imposed by INFLOW_QH (> 0 when used)
  *   h_out      depth imposed by FIXED_DEPTH (> 0 when used)
+ *   dir_left, dir_right  DIRICHLET ghost {h > 0, q, z, dz/dt} of the left / right end
  *   ks         Strickler coefficient K_s of the friction slope (>= 0; 0 = no friction source;
  *              MPM and VANRIJN need ks > 0, their Shields stress and shear velocity use s_f)
  *   precision  DSVE_FP64: all arithmetic in FP64.
@@ -121,6 +126,8 @@ typedef struct {
     double h_in;
     double h_out;
     double ks;
+    double dir_left[4];
+    double dir_right[4];
 } dsve_params;
 
 /* Per-channel parameters of a batched context (meaning and ranges as in dsve_params). */
@@ -133,6 +140,8 @@ typedef struct {
     double h_out;
     double ks;
     double law_extra[4];
+    double dir_left[4];
+    double dir_right[4];
     int bc_left, bc_right;
 } dsve_channel;
 
@@ -150,7 +159,7 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
  *   offsets[n_channels+1]  cell offsets, offsets[0] = 0, strictly increasing
  *   channels[n_channels]   per-channel parameters (each checked as in dsve_params)
  * g, law, n_gauss, cfl and precision come from *common; its per-channel fields (A_g,
- * porosity, dx, bc_*, q_in, h_in, h_out, ks, law_extra) are ignored.  All channels share the
+ * porosity, dx, bc_*, q_in, h_in, h_out, ks, law_extra, dir_*) are ignored.  All channels share the
  * closure law; its parameters may differ per channel.  Each channel gets its own time step
  * and clock (Sec. 3, Eq. scheme per channel).  The arrays are copied; the caller keeps them. */
 dsve_status dsve_batch_init(dsve_ctx **out, int64_t n_channels, const int64_t *offsets,

@@ -32,6 +32,7 @@ BC_PERIODIC = 1
 BC_INFLOW_Q = 2
 BC_FIXED_DEPTH = 3
 BC_INFLOW_QH = 4
+BC_DIRICHLET = 5
 
 LAW_GRASS = 0       # q_s = A_g u^3                                   (Sec. 2, Eq. Grass)
 LAW_GRASS_THR = 1   # q_s = A_g (u - u_cr)^3, par = (u_cr,)           (Sec. 2, Eq. GrassThr)
@@ -46,7 +47,7 @@ _CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-s
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no FMA contraction, no fast-math)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
+        tmp = f"{_LIB_PATH}.{os.getpid()}.tmp"
         subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -67,6 +68,8 @@ class Channel(ctypes.Structure):
         ("q_in", ctypes.c_double),
         ("h_out", ctypes.c_double),
         ("h_in", ctypes.c_double),
+        ("dir_l", ctypes.c_double * 4),
+        ("dir_r", ctypes.c_double * 4),
         ("law", ctypes.c_int),
         ("par", ctypes.c_double * 4),
         ("ks", ctypes.c_double),
@@ -240,6 +243,8 @@ class ChannelSpec:
     q_in: float = 0.0
     h_out: float = 0.0
     h_in: float = 0.0
+    dir_left: tuple = (0.0, 0.0, 0.0, 0.0)    # Dirichlet ghost (h, q, z at t = 0, dz/dt)
+    dir_right: tuple = (0.0, 0.0, 0.0, 0.0)
     law: int = LAW_GRASS
     par: tuple = ()
     ks: float = 0.0
@@ -248,7 +253,8 @@ class ChannelSpec:
         pr = list(self.par) + [0.0] * (4 - len(self.par))
         return Channel(self.n_cells, self.g, 1.0 / (1.0 - self.porosity), self.Ag, self.n_gauss,
                        self.cfl, self.dx, self.bc_left, self.bc_right, self.q_in, self.h_out,
-                       self.h_in, self.law, (ctypes.c_double * 4)(*pr), self.ks)
+                       self.h_in, (ctypes.c_double * 4)(*self.dir_left),
+                       (ctypes.c_double * 4)(*self.dir_right), self.law, (ctypes.c_double * 4)(*pr), self.ks)
 
 
 def run(spec: ChannelSpec, h, q, z, n_steps: int, t0: float = 0.0, nthreads: int | None = None,

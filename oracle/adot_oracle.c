@@ -46,6 +46,7 @@
 #define OR_BC_INFLOW_Q 2
 #define OR_BC_FIXED_DEPTH 3
 #define OR_BC_INFLOW_QH 4
+#define OR_BC_DIRICHLET 5
 
 #define OR_LAW_GRASS 0
 #define OR_LAW_GRASS_THR 1
@@ -88,6 +89,7 @@ typedef struct {
     double q_in;  /* discharge imposed by an inflow-q boundary */
     double h_out; /* depth imposed by a fixed-depth boundary */
     double h_in;  /* depth imposed with q_in by an inflow-(q, h) boundary */
+    double dir_l[4], dir_r[4]; /* Dirichlet ghost (h, q, z at t = 0, dz/dt) of each end */
     int law;
     double par[4];
     double ks;
@@ -621,9 +623,12 @@ int or_step(int64_t N, const double *h, const double *q, const double *z, const 
  * periodic = the cell at the other end; inflow-q = (h, q_in, z) of the adjacent cell;
  * fixed depth = (h_out, q, z) of the adjacent cell; inflow-(q, h) = (h_in, q_in, z) of the
  * adjacent cell (an imposed solid discharge enters through the depth h_in at which the
- * closure gives that q_s for q_in, Sec. 5.1). */
+ * closure gives that q_s for q_in, Sec. 5.1); Dirichlet = a given state whose bed level moves
+ * at a constant rate, (h_d, q_d, z_d + t dz/dt) at the time t of the step's start (the
+ * ghost cells of an analytical solution such as Sec. 4.2, Eq. berthon, whose bed falls
+ * linearly in time). */
 static void ghost_states(const or_channel *ch, const double *h, const double *q, const double *z,
-                         double gl[3], double gr[3])
+                         double t, double gl[3], double gr[3])
 {
     int64_t N = ch->n_cells;
     switch (ch->bc_left) {
@@ -631,6 +636,9 @@ static void ghost_states(const or_channel *ch, const double *h, const double *q,
     case OR_BC_INFLOW_Q: gl[0] = h[0]; gl[1] = ch->q_in; gl[2] = z[0]; break;
     case OR_BC_FIXED_DEPTH: gl[0] = ch->h_out; gl[1] = q[0]; gl[2] = z[0]; break;
     case OR_BC_INFLOW_QH: gl[0] = ch->h_in; gl[1] = ch->q_in; gl[2] = z[0]; break;
+    case OR_BC_DIRICHLET:
+        gl[0] = ch->dir_l[0]; gl[1] = ch->dir_l[1]; gl[2] = ch->dir_l[2] + t * ch->dir_l[3];
+        break;
     default: gl[0] = h[0]; gl[1] = q[0]; gl[2] = z[0]; break;
     }
     switch (ch->bc_right) {
@@ -638,6 +646,9 @@ static void ghost_states(const or_channel *ch, const double *h, const double *q,
     case OR_BC_INFLOW_Q: gr[0] = h[N - 1]; gr[1] = ch->q_in; gr[2] = z[N - 1]; break;
     case OR_BC_FIXED_DEPTH: gr[0] = ch->h_out; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
     case OR_BC_INFLOW_QH: gr[0] = ch->h_in; gr[1] = ch->q_in; gr[2] = z[N - 1]; break;
+    case OR_BC_DIRICHLET:
+        gr[0] = ch->dir_r[0]; gr[1] = ch->dir_r[1]; gr[2] = ch->dir_r[2] + t * ch->dir_r[3];
+        break;
     default: gr[0] = h[N - 1]; gr[1] = q[N - 1]; gr[2] = z[N - 1]; break;
     }
 }
@@ -647,7 +658,7 @@ static int check_channel(const or_channel *ch)
     if (ch->n_cells < 1) return OR_E_ARG;
     if (ch->n_gauss < 1 || ch->n_gauss > 64) return OR_E_ARG;
     if (!(ch->cfl > 0.0) || !(ch->dx > 0.0) || !(ch->g > 0.0) || !(ch->xi >= 1.0)) return OR_E_ARG;
-    if (ch->bc_left < 0 || ch->bc_left > 4 || ch->bc_right < 0 || ch->bc_right > 4) return OR_E_ARG;
+    if (ch->bc_left < 0 || ch->bc_left > 5 || ch->bc_right < 0 || ch->bc_right > 5) return OR_E_ARG;
     if ((ch->bc_left == OR_BC_PERIODIC) != (ch->bc_right == OR_BC_PERIODIC)) return OR_E_ARG;
     if (ch->law < OR_LAW_GRASS || ch->law > OR_LAW_VANRIJN) return OR_E_ARG;
     if ((ch->law == OR_LAW_MPM || ch->law == OR_LAW_VANRIJN) && !(ch->ks > 0.0)) return OR_E_ARG;
@@ -672,7 +683,7 @@ int or_run(const or_channel *ch, double *h, double *q, double *z, int n_steps, d
     int status = OR_OK;
     for (int n = 0; n < n_steps; ++n) {
         double gl[3], gr[3];
-        ghost_states(ch, h, q, z, gl, gr);
+        ghost_states(ch, h, q, z, *t, gl, gr);
         int nonhyp = 0;
         double amax = amax_of(N, h, q, z, &p, nthreads, &nonhyp);
         if (nonhyp) { status = OR_E_NONHYPERBOLIC; break; }

@@ -57,7 +57,7 @@ def build(verbose: bool = False, extra_device_flags=None, out: str | None = None
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = lib + ".tmp"
+    tmp = f"{lib}.{os.getpid()}.tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)

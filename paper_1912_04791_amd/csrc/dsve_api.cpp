@@ -1,7 +1,7 @@
 // dsve_api.cpp -- host side of libdsve.so: the C ABI declared in include/dsve.h.
 //
 // A context owns: per-channel records and edge offsets on the device, the tile table of the
-// fused step kernel, one ping-pong copy of the state, three rotating CFL-maximum slots per
+// fused step kernel, one ping-pong copy of the state and clocks, three rotating CFL-maximum slots per
 // channel, a flag word for deferred device errors, and a cached HIP graph of `graph_steps`
 // fused steps.  A run of n steps is: clear slots -> CFL max of W^0 into slot 0 -> graph
 // replays (each node is one step kernel; slot and ping-pong phase repeat every 6 steps, so
@@ -47,6 +47,7 @@ struct dsve_ctx {
     GaussRule rule{};
 
     double *pp_h = nullptr, *pp_q = nullptr, *pp_z = nullptr;   // ping-pong copy
+    double *pp_t = nullptr;                                      // ping-pong clocks [C]
     unsigned long long *d_amax = nullptr;                        // [3][C]
     unsigned int *d_flags = nullptr;                             // [4]
 
@@ -119,7 +120,7 @@ static bool gauss_rule(int G, GaussRule &r)
     return true;
 }
 
-static bool valid_bc(int b) { return b >= DSVE_BC_TRANSMISSIVE && b <= DSVE_BC_INFLOW_QH; }
+static bool valid_bc(int b) { return b >= DSVE_BC_TRANSMISSIVE && b <= DSVE_BC_DIRICHLET; }
 
 static dsve_status check_common(const dsve_params *p, std::string &msg)
 {
@@ -146,6 +147,14 @@ static dsve_status check_channel(int law, const dsve_channel &ch, std::string &m
     const bool uses_hout = ch.bc_left == DSVE_BC_FIXED_DEPTH || ch.bc_right == DSVE_BC_FIXED_DEPTH;
     if (uses_hin && !pos(ch.h_in)) { msg = "h_in must be > 0 for an inflow-(q, h) boundary"; return DSVE_E_ARG; }
     if (uses_hout && !pos(ch.h_out)) { msg = "h_out must be > 0 for a fixed-depth boundary"; return DSVE_E_ARG; }
+    for (int side = 0; side < 2; ++side) {
+        const double *d = side ? ch.dir_right : ch.dir_left;
+        if ((side ? ch.bc_right : ch.bc_left) != DSVE_BC_DIRICHLET) continue;
+        if (!pos(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]) || !std::isfinite(d[3])) {
+            msg = "a Dirichlet boundary needs h > 0 and finite q, z, dz/dt";
+            return DSVE_E_ARG;
+        }
+    }
     if (!(ch.ks >= 0.0) || !std::isfinite(ch.ks)) { msg = "ks must be finite and >= 0"; return DSVE_E_ARG; }
     const double *x = ch.law_extra;
     int used = 0;
@@ -228,6 +237,7 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     HIP_TRY(c, hipMalloc(&c->pp_h, sizeof(double) * c->n_cells));
     HIP_TRY(c, hipMalloc(&c->pp_q, sizeof(double) * c->n_cells));
     HIP_TRY(c, hipMalloc(&c->pp_z, sizeof(double) * c->n_cells));
+    HIP_TRY(c, hipMalloc(&c->pp_t, sizeof(double) * C));
     HIP_TRY(c, hipMalloc(&c->d_amax, sizeof(unsigned long long) * 3 * C));
     HIP_TRY(c, hipMalloc(&c->d_flags, sizeof(unsigned int) * 4));
     HIP_TRY(c, launch_fill_u64(c->d_amax, 3 * C, 0ull, c->stream));
@@ -250,6 +260,7 @@ static void release(dsve_ctx *c)
     (void)hipFree(c->pp_h);
     (void)hipFree(c->pp_q);
     (void)hipFree(c->pp_z);
+    (void)hipFree(c->pp_t);
     (void)hipFree(c->d_amax);
     (void)hipFree(c->d_flags);
     (void)hipFree(c->d_tile_chan);
@@ -269,9 +280,18 @@ static ChanInfo make_chan(int64_t cell0, int64_t n, int law, const dsve_channel 
     ci.K2 = 2.0 + 9.0 * ci.kqg;
     ci.cfl_dx = cfl * ch.dx;
     ci.inv_dx = 1.0 / ch.dx;
-    ci.q_in = ch.q_in;
-    ci.h_in = ch.h_in;
-    ci.h_out = ch.h_out;
+    // boundary data {h, q, z, dz/dt} of each end, as the ghost-state rules read them
+    for (int side = 0; side < 2; ++side) {
+        const int bc = side ? ch.bc_right : ch.bc_left;
+        double *b = side ? ci.br : ci.bl;
+        const double *d = side ? ch.dir_right : ch.dir_left;
+        if (bc == DSVE_BC_DIRICHLET) {
+            for (int k = 0; k < 4; ++k) b[k] = d[k];
+        } else {
+            b[0] = bc == DSVE_BC_FIXED_DEPTH ? ch.h_out : ch.h_in;
+            b[1] = ch.q_in;
+        }
+    }
     ci.fric = ch.ks > 0.0 ? 1.0 / (ch.ks * ch.ks) : 0.0;
     ci.law = law;
     const double *x = ch.law_extra;
@@ -317,6 +337,10 @@ static dsve_channel channel_of(const dsve_params *p)
     ch.q_in = p->q_in;
     ch.h_in = p->h_in;
     ch.h_out = p->h_out;
+    for (int k = 0; k < 4; ++k) {
+        ch.dir_left[k] = p->dir_left[k];
+        ch.dir_right[k] = p->dir_right[k];
+    }
     ch.ks = p->ks;
     for (int k = 0; k < 4; ++k) ch.law_extra[k] = p->law_extra[k];
     ch.bc_left = p->bc_left;
@@ -499,7 +523,8 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
     a.amax_cur = ctx->d_amax + (j % 3) * C;
     a.amax_next = ctx->d_amax + ((j + 1) % 3) * C;
     a.amax_clear = ctx->d_amax + ((j + 2) % 3) * C;
-    a.t = t;
+    a.t_cur = even ? t : ctx->pp_t;
+    a.t_next = even ? ctx->pp_t : t;
     a.flags = ctx->d_flags;
     a.n_edges = ctx->n_edges;
     a.n_tiles = ctx->n_tiles;
@@ -582,6 +607,8 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
         HIP_TRY(ctx, hipMemcpyAsync(h, ctx->pp_h, bytes, hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(q, ctx->pp_q, bytes, hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(z, ctx->pp_z, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(t, ctx->pp_t, sizeof(double) * ctx->n_channels,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
     }
     ctx->last_amax_slot = n_steps % 3;
     return DSVE_OK;

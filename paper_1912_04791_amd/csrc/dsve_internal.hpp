@@ -3,13 +3,15 @@
 // Layout in HBM (all device memory):
 //   state      h[N], q[N], z[N] float64 SoA, channels back to back (caller's arrays
 //              plus one ping-pong copy owned by the context)
-//   ChanInfo   one 128-byte record per channel (offsets, closure constants, CFL constant,
+//   ChanInfo   one 160-byte record per channel (offsets, closure constants, CFL constant,
 //              1/dx, friction, boundary conditions)
 //   eoff       int64 [C+1]: first edge of each channel in the flat edge space;
 //              channel c has N_c + 1 edges, eoff[c] = off[c] + c, eoff[C] = total edges
 //   tile_chan  int32 per tile: channel of the tile's first edge
 //   amax       uint64 [3][C]: bit patterns of the per-channel CFL maximum, rotated
 //              through three slots (read n%3, atomic-max (n+1)%3, clear (n+2)%3)
+//   clocks     float64 [C] twice (the caller's array and the context's copy): step n reads one
+//              and writes t + dt to the other, so every thread sees the step's start time
 //   flags      uint32 [4]: [0] non-hyperbolic state seen
 #pragma once
 
@@ -18,7 +20,8 @@
 
 namespace dsve {
 
-enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2, BC_FIXED_DEPTH = 3, BC_INFLOW_QH = 4 };
+enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2, BC_FIXED_DEPTH = 3, BC_INFLOW_QH = 4,
+       BC_DIRICHLET = 5 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN = 4 };
 // Kernel variants by closure: the Grass law in closed non-dimensional form, or any law through
@@ -64,16 +67,17 @@ struct alignas(16) ChanInfo {
     double K1, K2;   // 1 + 3 kqg, 2 + 9 kqg (k1 = 3 + K1 Fr^2, k2 = Fr (18 - K2 Fr^2))
     double cfl_dx;   // cfl * dx  (dt = cfl_dx / amax)
     double inv_dx;   // 1 / dx
-    double q_in;     // discharge imposed by BC_INFLOW_Q / BC_INFLOW_QH
-    double h_in;     // depth imposed by BC_INFLOW_QH
-    double h_out;    // depth imposed by BC_FIXED_DEPTH
     double fric;     // 1 / K_s^2 of the friction slope (0: no friction source)
     double lp0, lp1; // law constants (above)
+    // Boundary data of the left / right end {h, q, z, dz/dt}: the ghost takes h from it for
+    // FIXED_DEPTH, INFLOW_QH and DIRICHLET, q for INFLOW_Q, INFLOW_QH and DIRICHLET, and
+    // z + t dz/dt for DIRICHLET; other components come from the adjacent cell.
+    double bl[4], br[4];
     int32_t bcl, bcr;
     int32_t law;
     int32_t pad;
 };
-static_assert(sizeof(ChanInfo) == 128, "ChanInfo layout changed");
+static_assert(sizeof(ChanInfo) == 160, "ChanInfo layout changed");
 
 struct GaussRule {
     double s[kMaxGauss];
@@ -89,7 +93,8 @@ struct StepArgs {
     const unsigned long long *amax_cur;  // [C] CFL max of W^n
     unsigned long long *amax_next;       // [C] CFL max of W^{n+1} (pre-cleared)
     unsigned long long *amax_clear;      // [C] slot to clear for step n+1
-    double *t;                   // [C] clocks
+    const double *t_cur;         // [C] clocks at the start of the step
+    double *t_next;              // [C] clocks after it
     unsigned int *flags;
     int64_t n_edges;
     int64_t n_tiles;

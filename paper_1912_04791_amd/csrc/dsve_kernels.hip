@@ -81,15 +81,19 @@ __device__ __forceinline__ double cell_speed(double h, double q, double g, const
     else return speed_mixed<CL>(h, q, g, K, bad);
 }
 
-// Ghost states (boundary conditions): depth and discharge beyond edge 0 (left) or edge N
-// (right) of a channel from the adjacent cell's (h, q); the bed is always the adjacent cell's.
-__device__ __forceinline__ double ghost_h(int bc, const ChanInfo &ci, double h)
+// Ghost states (boundary conditions): the state beyond edge 0 (left) or edge N (right) of a
+// channel from the adjacent cell's and the end's boundary data b = {h, q, z, dz/dt}.
+__device__ __forceinline__ double ghost_h(int bc, const double *b, double h)
 {
-    return bc == BC_FIXED_DEPTH ? ci.h_out : (bc == BC_INFLOW_QH ? ci.h_in : h);
+    return (bc == BC_FIXED_DEPTH || bc == BC_INFLOW_QH || bc == BC_DIRICHLET) ? b[0] : h;
 }
-__device__ __forceinline__ double ghost_q(int bc, const ChanInfo &ci, double q)
+__device__ __forceinline__ double ghost_q(int bc, const double *b, double q)
 {
-    return (bc == BC_INFLOW_Q || bc == BC_INFLOW_QH) ? ci.q_in : q;
+    return (bc == BC_INFLOW_Q || bc == BC_INFLOW_QH || bc == BC_DIRICHLET) ? b[1] : q;
+}
+__device__ __forceinline__ double ghost_z(int bc, const double *b, double z, double t)
+{
+    return bc == BC_DIRICHLET ? fma(t, b[3], b[2]) : z;
 }
 
 // ---------------------------------------------------------------------------
@@ -123,17 +127,21 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             const int64_t ir = (e == N) ? (ci.bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
             double hL = A.h[il];
             double qL = A.q[il];
-            const double zL = A.z[il];
+            double zL = A.z[il];
             hR = A.h[ir];
             qR = A.q[ir];
             zR = A.z[ir];
+            double hRe = hR, qRe = qR, zRe = zR;
             if (e == 0) {
-                hL = ghost_h(ci.bcl, ci, hL);
-                qL = ghost_q(ci.bcl, ci, qL);
+                hL = ghost_h(ci.bcl, ci.bl, hL);
+                qL = ghost_q(ci.bcl, ci.bl, qL);
+                if (ci.bcl == BC_DIRICHLET) zL = ghost_z(ci.bcl, ci.bl, zL, A.t_cur[c]);
+            } else if (e == N) {
+                hRe = ghost_h(ci.bcr, ci.br, hR);
+                qRe = ghost_q(ci.bcr, ci.br, qR);
+                if (ci.bcr == BC_DIRICHLET) zRe = ghost_z(ci.bcr, ci.br, zR, A.t_cur[c]);
             }
-            const double hRe = (e == N) ? ghost_h(ci.bcr, ci, hR) : hR;
-            const double qRe = (e == N) ? ghost_q(ci.bcr, ci, qR) : qR;
-            edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zR, A.g, K, A.rule, Dm, Dp, bad);
+            edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zRe, A.g, K, A.rule, Dm, Dp, bad);
         }
         s_dm[t] = Dm[0];
         s_dm[T + t] = Dm[1];
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             const double sp = fabs(cell_speed<PREC, CL>(hn, qn, A.g, K, bad));
             sp_bits = (unsigned long long)__double_as_longlong(sp);
             if (e == 0) {
-                A.t[c] += dt;
+                A.t_next[c] = A.t_cur[c] + dt;
                 A.amax_clear[c] = 0ull;
             }
         }

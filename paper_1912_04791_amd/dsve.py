@@ -27,6 +27,7 @@ BC_PERIODIC = 1
 BC_INFLOW_Q = 2
 BC_FIXED_DEPTH = 3
 BC_INFLOW_QH = 4
+BC_DIRICHLET = 5
 LAW_GRASS = 0
 LAW_GRASS_THR = 1
 LAW_POWER = 2
@@ -60,6 +61,8 @@ class Params(ctypes.Structure):
         ("h_in", ctypes.c_double),
         ("h_out", ctypes.c_double),
         ("ks", ctypes.c_double),
+        ("dir_left", ctypes.c_double * 4),
+        ("dir_right", ctypes.c_double * 4),
     ]
 
 
@@ -74,6 +77,8 @@ class Channel(ctypes.Structure):
         ("h_out", ctypes.c_double),
         ("ks", ctypes.c_double),
         ("law_extra", ctypes.c_double * 4),
+        ("dir_left", ctypes.c_double * 4),
+        ("dir_right", ctypes.c_double * 4),
         ("bc_left", ctypes.c_int),
         ("bc_right", ctypes.c_int),
     ]
@@ -137,7 +142,7 @@ def _stream_handle(stream) -> int:
 def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
                 bc_left=BC_TRANSMISSIVE, bc_right=BC_TRANSMISSIVE, q_in=0.0,
                 precision="fp64", law=LAW_GRASS, law_extra=(), h_in=0.0, h_out=0.0,
-                ks=0.0) -> Params:
+                ks=0.0, dir_left=(0.0, 0.0, 0.0, 0.0), dir_right=(0.0, 0.0, 0.0, 0.0)) -> Params:
     p = Params()
     p.g = g
     p.porosity = porosity
@@ -156,17 +161,21 @@ def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
     p.h_in = h_in
     p.h_out = h_out
     p.ks = ks
+    for k in range(4):
+        p.dir_left[k] = float(dir_left[k])
+        p.dir_right[k] = float(dir_right[k])
     return p
 
 
 def make_channels(A_g, porosity, dx, bc_left, bc_right, q_in=None, h_in=None, h_out=None,
-                  ks=None, law_extra=None):
+                  ks=None, law_extra=None, dir_left=None, dir_right=None):
     """A ``dsve_channel`` array from per-channel arrays (missing ones are zero)."""
     C = len(A_g)
     z = np.zeros(C)
     cols = [np.asarray(a if a is not None else z, dtype=np.float64)
             for a in (A_g, porosity, dx, q_in, h_in, h_out, ks)]
-    ex = np.zeros((C, 4)) if law_extra is None else np.asarray(law_extra, dtype=np.float64).reshape(C, 4)
+    four = lambda a: np.zeros((C, 4)) if a is None else np.asarray(a, dtype=np.float64).reshape(C, 4)
+    ex, dl, dr = four(law_extra), four(dir_left), four(dir_right)
     bcl = np.asarray(bc_left, dtype=np.int32)
     bcr = np.asarray(bc_right, dtype=np.int32)
     for a in (*cols, bcl, bcr):
@@ -177,6 +186,8 @@ def make_channels(A_g, porosity, dx, bc_left, bc_right, q_in=None, h_in=None, h_
         ch.A_g, ch.porosity, ch.dx, ch.q_in, ch.h_in, ch.h_out, ch.ks = (float(a[c]) for a in cols)
         for k in range(4):
             ch.law_extra[k] = float(ex[c, k])
+            ch.dir_left[k] = float(dl[c, k])
+            ch.dir_right[k] = float(dr[c, k])
         ch.bc_left = int(bcl[c])
         ch.bc_right = int(bcr[c])
     return arr
@@ -203,11 +214,12 @@ class Context:
 
     @classmethod
     def batch(cls, offsets, A_g, porosity, dx, bc_left, bc_right, q_in=None, stream=None,
-              h_in=None, h_out=None, ks=None, law_extra=None, **common) -> "Context":
+              h_in=None, h_out=None, ks=None, law_extra=None, dir_left=None, dir_right=None,
+              **common) -> "Context":
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         C = off.size - 1
         chans = make_channels(A_g, porosity, dx, bc_left, bc_right, q_in, h_in, h_out, ks,
-                              law_extra)
+                              law_extra, dir_left, dir_right)
         assert len(chans) == C
         p = make_params(**common)
         h = _ctxp()
@@ -228,11 +240,12 @@ class Context:
                               bc_right=int(wl.bc_right[0]), q_in=float(wl.q_in[0]),
                               precision=prec, law=wl.law, law_extra=tuple(wl.law_par[0]),
                               h_in=float(wl.h_in[0]), h_out=float(wl.h_out[0]),
-                              ks=float(wl.ks[0]))
+                              ks=float(wl.ks[0]), dir_left=tuple(wl.dir_left[0]),
+                              dir_right=tuple(wl.dir_right[0]))
         return cls.batch(wl.offsets, wl.Ag, wl.porosity, wl.dx, wl.bc_left, wl.bc_right, wl.q_in,
                          stream=stream, h_in=wl.h_in, h_out=wl.h_out, ks=wl.ks,
-                         law_extra=wl.law_par, g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl,
-                         precision=prec, law=wl.law)
+                         law_extra=wl.law_par, dir_left=wl.dir_left, dir_right=wl.dir_right,
+                         g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl, precision=prec, law=wl.law)
 
     # -- helpers ----------------------------------------------------------
     def _check(self, st: int, what: str):

@@ -40,6 +40,8 @@ shaped like the paper's laboratory cases (their measured data are not used):
   N_c in {512..4096}, q0 ~ U[0.015, 0.025], s0 ~ U[3e-3, 4e-3], K_s ~ U[45, 55], an
   overfeeding factor F ~ U[2, 5] (h_in = F^(-1/5) h0) and h0 = (q0^2 / (K_s^2 s0))^(3/10),
   the uniform-flow depth of the friction law.
+* ``berthon`` -- the smooth analytical solution of Sec. 4.2 (Test 2) on N cells, Dirichlet
+  ghost cells carrying the exact solution, for the error E_phi of Eq. Eg against the closed form.
 * ``bellal_<law>`` -- sediment bore in a steep flume (Sec. 5.2): 6.9 m, s0 = 3.02e-2,
   q0 = 0.024 m^2/s (12 l/s over 0.5 m), d50 = 1.65 mm, porosity 0.42, K_s = 62, S_g = 2.6,
   nu = 1e-6, theta_cr = 0.03; start from the uniform flow h0 = (q0^2 / (K_s^2 s0))^(3/10)
@@ -68,6 +70,7 @@ BC_PERIODIC = 1
 BC_INFLOW_Q = 2
 BC_FIXED_DEPTH = 3
 BC_INFLOW_QH = 4
+BC_DIRICHLET = 5
 
 LAW_GRASS = 0
 LAW_GRASS_THR = 1
@@ -77,7 +80,7 @@ LAW_VANRIJN = 4
 
 # per-channel array fields of a Workload, in the order channel()/subset() copy them
 PER_CHANNEL = ("dx", "Ag", "porosity", "bc_left", "bc_right", "q_in", "h_in", "h_out", "ks",
-               "law_par")
+               "law_par", "dir_left", "dir_right")
 
 
 @dataclass
@@ -106,12 +109,15 @@ class Workload:
     ks: np.ndarray | None = None        # float64 [C] Strickler coefficient (0: no friction)
     h_in: np.ndarray | None = None      # float64 [C] depth of an inflow-(q, h) boundary
     h_out: np.ndarray | None = None     # float64 [C] depth of a fixed-depth boundary
+    dir_left: np.ndarray | None = None  # float64 [C, 4] Dirichlet ghost (h, q, z, dz/dt), left
+    dir_right: np.ndarray | None = None  # float64 [C, 4] the same, right
 
     def __post_init__(self):
         C = self.offsets.size - 1
-        if self.law_par is None:
-            self.law_par = np.zeros((C, 4))
-        self.law_par = np.ascontiguousarray(np.asarray(self.law_par, dtype=np.float64).reshape(C, 4))
+        for f in ("law_par", "dir_left", "dir_right"):
+            v = getattr(self, f)
+            v = np.zeros((C, 4)) if v is None else np.asarray(v, dtype=np.float64).reshape(C, 4)
+            setattr(self, f, np.ascontiguousarray(v))
         for f in ("ks", "h_in", "h_out"):
             v = getattr(self, f)
             setattr(self, f, np.zeros(C) if v is None else np.asarray(v, dtype=np.float64).reshape(C))
@@ -422,6 +428,42 @@ def make_bellal(law: str = "mpm", n_channels: int = 8192, len_lo: int = 512, len
     return _assemble(f"bellal_{law}", parts, L / lens, Ag, np.full(C, por),
                      np.full(C, BC_INFLOW_QH), np.full(C, BC_FIXED_DEPTH), steps, seed, q_in=q0v,
                      law=code, law_par=par, ks=ksv, h_in=h0v, h_out=houtv)
+
+
+# ---------------------------------------------------------------------------
+# Smooth analytical solution of Sec. 4.2 (Test 2): steady subcritical flow over a bed eroding
+# linearly in time.  alpha = beta = A_g = 0.005, C = 1, L = 7 m, t_end = 10 s are printed in
+# the paper; q0 is not, and q0 = 1 m^2/s (subcritical on [0, L]) is a reading; xi = 1
+# (porosity 0), which the printed bed law z(x, t) = z(x, 0) - alpha t requires.
+BERTHON = {"alpha": 0.005, "beta": 0.005, "A_g": 0.005, "C": 1.0, "L": 7.0, "t_end": 10.0,
+           "q0": 1.0}
+
+
+def berthon_exact(x, t: float, g: float = G_ACC):
+    """(h, q, z) of the analytical solution at positions x and time t."""
+    a, b, Ag, C, q0 = (BERTHON[k] for k in ("alpha", "beta", "A_g", "C", "q0"))
+    u = ((a * np.asarray(x, dtype=np.float64) + b) / Ag) ** (1.0 / 3.0)
+    return q0 / u, np.full_like(u, q0), -(u ** 3 + 2.0 * g * q0) / (2.0 * g * u) + C - a * t
+
+
+def make_berthon(n_cells: int = 300, steps: int = 0) -> Workload:
+    """Test 2 on N cells: the exact solution at t = 0 as initial state, Dirichlet ghost cells
+    carrying the exact solution at the ghost centres (the bed falling at the rate alpha).
+    ``steps`` 0 gives an estimate of the steps to t_end (CFL 0.9 with max |u| + c)."""
+    L = BERTHON["L"]
+    dx = L / n_cells
+    x = cell_centres(n_cells, L)
+    h, q, z = berthon_exact(x, 0.0)
+    gh, gq, gz = berthon_exact(np.array([-0.5 * dx, L + 0.5 * dx]), 0.0)
+    rate = -BERTHON["alpha"]
+    if steps <= 0:
+        speed = np.max(np.abs(q / h) + np.sqrt(G_ACC * h))
+        steps = int(np.ceil(BERTHON["t_end"] / (0.9 * dx / speed)))
+    wl = _single("berthon", h, q, z, dx, BERTHON["A_g"], 0.0, BC_DIRICHLET, BC_DIRICHLET, 0.0,
+                 steps, dir_left=np.array([[gh[0], gq[0], gz[0], rate]]),
+                 dir_right=np.array([[gh[1], gq[1], gz[1], rate]]))
+    wl.meta["x"] = x
+    return wl
 
 
 def make_lake_at_rest(n_cells: int = 400, length: float = 10.0, level: float = 1.0,

@@ -11,7 +11,9 @@ def spec_of(wl: inputs.Workload, c: int = 0) -> "oracle.ChannelSpec":
                               cfl=wl.cfl, bc_left=int(wl.bc_left[c]), bc_right=int(wl.bc_right[c]),
                               q_in=float(wl.q_in[c]), h_out=float(wl.h_out[c]),
                               h_in=float(wl.h_in[c]), law=int(wl.law),
-                              par=tuple(float(v) for v in wl.law_par[c]), ks=float(wl.ks[c]))
+                              par=tuple(float(v) for v in wl.law_par[c]), ks=float(wl.ks[c]),
+                              dir_left=tuple(float(v) for v in wl.dir_left[c]),
+                              dir_right=tuple(float(v) for v in wl.dir_right[c]))
 
 
 def oracle_run(wl: inputs.Workload, steps: int | None = None, nthreads: int | None = None):

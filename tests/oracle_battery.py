@@ -111,6 +111,20 @@ def checks(lib):
         out["inflow_qh"] = bool(np.array_equal(hr, hs) and np.array_equal(qr, qs2))
     except oracle.OracleError:
         out["inflow_qh"] = False
+    # Dirichlet ghosts with a moving bed: after two steps the left ghost's bed has moved
+    spec = oracle.ChannelSpec(n_cells=32, dx=0.1, Ag=0.01, porosity=0.4,
+                              bc_left=oracle.BC_DIRICHLET, bc_right=oracle.BC_DIRICHLET,
+                              dir_left=(0.97, 0.31, 0.02, -0.5), dir_right=(1.02, 0.29, -0.01, 0.0))
+    try:
+        h1, q1, z1, t1 = oracle.run(spec, hb, qb, zb, 1, nthreads=2, lib=lib)
+        hr, qr, zr, t2 = oracle.run(spec, h1, q1, z1, 1, t0=t1, nthreads=2, lib=lib)
+        am = oracle.cfl_amax(h1, q1, z1, G, 1 / 0.6, 0.01, lib=lib)
+        hs, qs2, zs = oracle.step(h1, q1, z1, [0.97, 0.31, 0.02 - 0.5 * t1], [1.02, 0.29, -0.01], G,
+                                  1 / 0.6, 0.01, 3, 0.9 * 0.1 / am, 0.1, lib=lib)
+        out["dirichlet"] = bool(np.allclose(hr, hs, rtol=1e-14, atol=0) and
+                                np.allclose(zr, zs, rtol=1e-14, atol=1e-16))
+    except oracle.OracleError:
+        out["dirichlet"] = False
 
     for name, wl, periodic in (("scheme_c1", inputs.make_c1(n_cells=120, steps=25), False),
                                ("scheme_periodic", inputs.make_c2(n_cells=256, steps=25), True)):

@@ -70,7 +70,8 @@ def test_argument_errors_without_device_work():
         dict(law=dsve.LAW_GRASS, law_extra=(1.0,)),                             # unused entry
         dict(bc_right=dsve.BC_FIXED_DEPTH),                                      # no h_out
         dict(bc_left=dsve.BC_INFLOW_QH, q_in=0.1),                               # no h_in
-        dict(bc_left=5),
+        dict(bc_left=dsve.BC_DIRICHLET, bc_right=dsve.BC_DIRICHLET),            # no ghost depth
+        dict(bc_left=6),
         dict(ks=-1.0),
     ]
     for kw in bad:

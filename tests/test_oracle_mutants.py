@@ -60,6 +60,7 @@ MUTANTS = {
                          "return q * fabs(q) / (ks * ks * pow(h, 7.0 / 3.0));"),
     "fixed_depth_ghost": ("case OR_BC_FIXED_DEPTH: gr[0] = ch->h_out;", "case OR_BC_FIXED_DEPTH: gr[0] = h[N - 1];"),
     "inflow_qh_ghost_depth": ("case OR_BC_INFLOW_QH: gl[0] = ch->h_in;", "case OR_BC_INFLOW_QH: gl[0] = h[0];"),
+    "dirichlet_drift_sign": ("gl[2] = ch->dir_l[2] + t * ch->dir_l[3];", "gl[2] = ch->dir_l[2] - t * ch->dir_l[3];"),
     "periodic_ghost_wrong_end": ("case OR_BC_PERIODIC: gl[0] = h[N - 1]; gl[1] = q[N - 1]; gl[2] = z[N - 1];",
                                  "case OR_BC_PERIODIC: gl[0] = h[0]; gl[1] = q[0]; gl[2] = z[0];"),
 }

@@ -95,6 +95,33 @@ def _berthon_run(orc, fx, n):
     return err(h, he), err(q, qe), err(z, ze)
 
 
+def test_dirichlet_boundary_carries_the_exact_ghosts(orc):
+    # the Dirichlet ghost (h, q, z at t = 0, dz/dt) of or_run reproduces the explicit exact-ghost
+    # loop (same steps, ghosts evaluated at each step's start)
+    with open(os.path.join(GOLDEN, "berthon_test2.json")) as f:
+        fx = json.load(f)
+    exact = _berthon(fx)
+    L, g, xi, Ag, a = fx["L"], fx["g"], fx["xi"], fx["A_g"], fx["alpha"]
+    n, steps = 160, 60
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    h, q, z = exact(x, 0.0)
+    gh, gq, gz = exact(np.array([-0.5 * dx, L + 0.5 * dx]), 0.0)
+    spec = orc.ChannelSpec(n_cells=n, dx=dx, Ag=Ag, porosity=1.0 - 1.0 / xi, g=g,
+                           bc_left=orc.BC_DIRICHLET, bc_right=orc.BC_DIRICHLET,
+                           dir_left=(gh[0], gq[0], gz[0], -a), dir_right=(gh[1], gq[1], gz[1], -a))
+    h1, q1, z1, t1 = orc.run(spec, h, q, z, steps)
+    t = 0.0
+    for _ in range(steps):
+        dt = 0.9 * dx / orc.cfl_amax(h, q, z, g, xi, Ag)
+        gh, gq, gz = exact(np.array([-0.5 * dx, L + 0.5 * dx]), t)
+        h, q, z = orc.step(h, q, z, [gh[0], gq[0], gz[0]], [gh[1], gq[1], gz[1]], g, xi, Ag, 3, dt, dx)
+        t += dt
+    assert abs(t1 - t) <= 1e-13 * t
+    for a1, r in ((h1, h), (q1, q), (z1, z)):
+        np.testing.assert_allclose(a1, r, rtol=1e-13, atol=1e-14)
+
+
 def test_first_order_convergence_smooth_solution(orc):
     with open(os.path.join(GOLDEN, "berthon_test2.json")) as f:
         fx = json.load(f)
