@@ -83,12 +83,12 @@ def _descriptions():
     return inputs.DESCRIPTIONS
 
 
-def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None):
+def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: str = "adot"):
     import torch
     from paper_1912_04791_amd import dsve
 
     stream = torch.cuda.current_stream()
-    ctx = dsve.Context.from_workload(wl, precision=precision, stream=stream)
+    ctx = dsve.Context.from_workload(wl, precision=precision, stream=stream, solver=solver)
     if launch:
         ctx.set_launch(*launch)
     h, q, z, t = dsve.upload(wl)
@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--precisions", default=None,
                     help="comma list; default fp64,mixed (mixed,fp64 for the mixed workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--dot-steps", type=int, default=100,
+                    help="steps timed for the original DOT (numerical eigensolver) baseline; 0 skips it")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=-1)
@@ -293,6 +295,19 @@ def main():
                      "roofline": {"bound": "alu", "achieved": achieved_p, "peak": peak_p,
                                   "unit": "TFLOP/s", "frac": achieved_p / peak_p,
                                   "traffic": measured_traffic(wl.name, prec)}}
+
+    if args.dot_steps > 0:
+        # the paper's own baseline: the same scheme with the numerical eigen-decomposition
+        r = time_gpu(wl, "fp64", args.dot_steps, min(args.warmup, 6), launch, solver="dot")
+        v = edges * args.dot_steps / (r["ms_total"] * 1e-3)
+        print(f"[bench] {wl.name} dot fp64: {r['ms_total'] / args.dot_steps * 1e3:.2f} us/step, "
+              f"{v:.4e} edge-updates/s", file=sys.stderr, flush=True)
+        adot64 = results.get("fp64")
+        out["dot_fp64"] = {"value": v, "ms_per_step": r["ms_total"] / args.dot_steps,
+                           "steps": args.dot_steps,
+                           "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
+                                      "graph_steps": r["launch"][2]},
+                           "adot_fp64_speedup": (adot64["edge_updates_per_s"] / v) if adot64 else None}
 
     if not args.no_cpu:
         base, ref, n, chans = cpu_baseline(wl)

@@ -89,6 +89,12 @@ enum { DSVE_BC_TRANSMISSIVE = 0, DSVE_BC_PERIODIC = 1, DSVE_BC_INFLOW_Q = 2,
 enum { DSVE_LAW_GRASS = 0, DSVE_LAW_GRASS_THR = 1, DSVE_LAW_POWER = 2, DSVE_LAW_MPM = 3,
        DSVE_LAW_VANRIJN = 4 };
 enum { DSVE_FP64 = 0, DSVE_MIXED = 1 };
+/* Eigenstructure of the flux matrix at each quadrature node:
+ *   ADOT  the closed form of Sec. 3.3 (the A-DOT scheme)
+ *   DOT   a generic numerical eigen-decomposition, the original DOT solver of Sec. 3.1 (real
+ *         Schur form by shifted QR, eigenvectors by back substitution, R^-1 by LU with partial
+ *         pivoting, |A| = R |Lambda| R^-1): the baseline the closed form replaces; FP64 only */
+enum { DSVE_SOLVER_ADOT = 0, DSVE_SOLVER_DOT = 1 };
 
 /* Parameters of a context.
  *   g          gravitational acceleration (> 0)
@@ -106,6 +112,8 @@ enum { DSVE_FP64 = 0, DSVE_MIXED = 1 };
  *   dir_left, dir_right  DIRICHLET ghost {h > 0, q, z, dz/dt} of the left / right end
  *   ks         Strickler coefficient K_s of the friction slope (>= 0; 0 = no friction source;
  *              MPM and VANRIJN need ks > 0, their Shields stress and shear velocity use s_f)
+ *   solver     DSVE_SOLVER_ADOT (default) or DSVE_SOLVER_DOT; DOT with DSVE_MIXED is
+ *              DSVE_E_UNSUPPORTED
  *   precision  DSVE_FP64: all arithmetic in FP64.
  *              DSVE_MIXED: eigenstructure and quadrature in FP32; FP64 for the
  *              jumps W+ - W-, for the cubic's root solve and the eigenvector
@@ -128,6 +136,7 @@ typedef struct {
     double ks;
     double dir_left[4];
     double dir_right[4];
+    int solver;
 } dsve_params;
 
 /* Per-channel parameters of a batched context (meaning and ranges as in dsve_params). */
@@ -158,7 +167,7 @@ dsve_status dsve_init(dsve_ctx **out, const dsve_params *p, int64_t n_cells, voi
  * HOST arrays:
  *   offsets[n_channels+1]  cell offsets, offsets[0] = 0, strictly increasing
  *   channels[n_channels]   per-channel parameters (each checked as in dsve_params)
- * g, law, n_gauss, cfl and precision come from *common; its per-channel fields (A_g,
+ * g, law, n_gauss, cfl, precision and solver come from *common; its per-channel fields (A_g,
  * porosity, dx, bc_*, q_in, h_in, h_out, ks, law_extra, dir_*) are ignored.  All channels share the
  * closure law; its parameters may differ per channel.  Each channel gets its own time step
  * and clock (Sec. 3, Eq. scheme per channel).  The arrays are copied; the caller keeps them. */

@@ -130,6 +130,11 @@ static dsve_status check_common(const dsve_params *p, std::string &msg)
     if (p->n_gauss < 1 || p->n_gauss > 5) { msg = "n_gauss must be in [1, 5]"; return DSVE_E_ARG; }
     if (!(p->cfl > 0.0 && p->cfl <= 1.0)) { msg = "cfl must be in (0, 1]"; return DSVE_E_ARG; }
     if (p->precision != DSVE_FP64 && p->precision != DSVE_MIXED) { msg = "unknown precision"; return DSVE_E_ARG; }
+    if (p->solver != DSVE_SOLVER_ADOT && p->solver != DSVE_SOLVER_DOT) { msg = "unknown solver"; return DSVE_E_ARG; }
+    if (p->solver == DSVE_SOLVER_DOT && p->precision != DSVE_FP64) {
+        msg = "the numerical-eigensolver DOT runs in FP64 only";
+        return DSVE_E_UNSUPPORTED;
+    }
     return DSVE_OK;
 }
 
@@ -350,7 +355,8 @@ static dsve_channel channel_of(const dsve_params *p)
 
 static void set_common(dsve_ctx *c, const dsve_params *p)
 {
-    c->precision = p->precision;
+    // kernel arithmetic: the precision, or the numerical eigensolver of the original DOT
+    c->precision = p->solver == DSVE_SOLVER_DOT ? PREC_DOT : p->precision;
     c->law = p->law;
     c->cl = p->law == DSVE_LAW_GRASS ? CL_GRASS : CL_LAW;
     c->G = p->n_gauss;

@@ -22,7 +22,9 @@ namespace dsve {
 
 enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2, BC_FIXED_DEPTH = 3, BC_INFLOW_QH = 4,
        BC_DIRICHLET = 5 };
-enum { PREC_FP64 = 0, PREC_MIXED = 1 };
+// Arithmetic of a kernel: FP64 closed form, mixed FP32/FP64 closed form, or FP64 with the
+// numerical eigen-decomposition of the original DOT solver (the baseline of the closed form).
+enum { PREC_FP64 = 0, PREC_MIXED = 1, PREC_DOT = 2 };
 enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN = 4 };
 // Kernel variants by closure: the Grass law in closed non-dimensional form, or any law through
 // the per-state coefficient b = xi dq_s/dq.
@@ -45,9 +47,13 @@ constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step
 #ifndef DSVE_MINW_LAW_MIXED
 #define DSVE_MINW_LAW_MIXED 2
 #endif
+#ifndef DSVE_MINW_DOT
+#define DSVE_MINW_DOT 2
+#endif
 constexpr int step_min_waves(int prec, int cl)
 {
-    return cl == CL_GRASS ? (prec == PREC_FP64 ? DSVE_MINW_FP64 : DSVE_MINW_MIXED)
+    return prec == PREC_DOT ? DSVE_MINW_DOT
+         : cl == CL_GRASS ? (prec == PREC_FP64 ? DSVE_MINW_FP64 : DSVE_MINW_MIXED)
                           : (prec == PREC_FP64 ? DSVE_MINW_LAW_FP64 : DSVE_MINW_LAW_MIXED);
 }
 
@@ -125,7 +131,7 @@ struct FluctArgs {
 };
 
 // Host-side launchers (dsve_kernels.hip).  All enqueue on `stream` and return the
-// hipError_t of the launch.
+// hipError_t of the launch; `precision` is one of PREC_*.
 hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
                        hipStream_t stream);
 // Workgroups of the step kernel that fit on one compute unit at once (occupancy query).

@@ -9,7 +9,9 @@
 // k_update    cell update from given fluctuations (cell_update entry point).
 //
 // Every kernel comes in two closure forms: CL_GRASS (the Grass law in closed form, the
-// workloads of Sec. 4) and CL_LAW (any closure through b = xi dq_s/dq per state).
+// workloads of Sec. 4) and CL_LAW (any closure through b = xi dq_s/dq per state), and in three
+// arithmetic forms: FP64 and mixed closed form (Sec. 3.3), and FP64 with the numerical
+// eigen-decomposition of the original DOT solver (Sec. 3.1), the baseline of the closed form.
 //
 // Tiling of the step kernel: a workgroup of T threads takes T consecutive edges of the flat
 // edge space and updates the T-1 cells whose two faces both lie in the tile; tile k starts at
@@ -19,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dsve_dot.hpp"
 #include "dsve_internal.hpp"
 #include "dsve_math.hpp"
 
@@ -70,7 +73,8 @@ __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, doub
                                            bool &bad)
 {
     if constexpr (PREC == PREC_FP64) fluct64<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
-    else fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    else if constexpr (PREC == PREC_MIXED) fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    else fluct_dot<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
 }
 
 template <int PREC, int CL>
@@ -78,7 +82,8 @@ __device__ __forceinline__ double cell_speed(double h, double q, double g, const
                                              bool &bad)
 {
     if constexpr (PREC == PREC_FP64) return speed64<CL>(h, q, g, K, bad);
-    else return speed_mixed<CL>(h, q, g, K, bad);
+    else if constexpr (PREC == PREC_MIXED) return speed_mixed<CL>(h, q, g, K, bad);
+    else return speed_dot<CL>(h, q, g, K, bad);
 }
 
 // Ghost states (boundary conditions): the state beyond edge 0 (left) or edge N (right) of a
@@ -357,6 +362,7 @@ int step_blocks_per_cu(int precision, int G, int cl, int tile)
 {
     int n = 0;
     const hipError_t e = precision == PREC_MIXED ? occupancy_query<PREC_MIXED>(G, cl, tile, n)
+                         : precision == PREC_DOT ? occupancy_query<PREC_DOT>(G, cl, tile, n)
                                                  : occupancy_query<PREC_FP64>(G, cl, tile, n);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
@@ -367,6 +373,7 @@ hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile
     if (tile < 64 || tile > kMaxTile || (tile & 63) || grid < 1) return hipErrorInvalidValue;
     if (precision == PREC_FP64) return launch_step_prec<PREC_FP64>(a, G, cl, tile, grid, stream);
     if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED>(a, G, cl, tile, grid, stream);
+    if (precision == PREC_DOT) return launch_step_prec<PREC_DOT>(a, G, cl, tile, grid, stream);
     return hipErrorNotSupported;
 }
 
@@ -381,6 +388,9 @@ hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t strea
     } else if (precision == PREC_MIXED) {
         if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_GRASS>), grid, block, 0, stream, a);
         else hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_LAW>), grid, block, 0, stream, a);
+    } else if (precision == PREC_DOT) {
+        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_DOT, CL_GRASS>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_cfl<PREC_DOT, CL_LAW>), grid, block, 0, stream, a);
     } else {
         return hipErrorNotSupported;
     }
@@ -392,6 +402,7 @@ hipError_t launch_fluct(const FluctArgs &a, int precision, int G, int cl, hipStr
     if (a.n < 1) return hipSuccess;
     if (precision == PREC_FP64) return launch_fluct_prec<PREC_FP64>(a, G, cl, stream);
     if (precision == PREC_MIXED) return launch_fluct_prec<PREC_MIXED>(a, G, cl, stream);
+    if (precision == PREC_DOT) return launch_fluct_prec<PREC_DOT>(a, G, cl, stream);
     return hipErrorNotSupported;
 }
 

@@ -36,6 +36,8 @@ LAW_VANRIJN = 4
 FP64 = 0
 MIXED = 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+SOLVER_ADOT = 0
+SOLVER_DOT = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -63,6 +65,7 @@ class Params(ctypes.Structure):
         ("ks", ctypes.c_double),
         ("dir_left", ctypes.c_double * 4),
         ("dir_right", ctypes.c_double * 4),
+        ("solver", ctypes.c_int),
     ]
 
 
@@ -142,7 +145,10 @@ def _stream_handle(stream) -> int:
 def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
                 bc_left=BC_TRANSMISSIVE, bc_right=BC_TRANSMISSIVE, q_in=0.0,
                 precision="fp64", law=LAW_GRASS, law_extra=(), h_in=0.0, h_out=0.0,
-                ks=0.0, dir_left=(0.0, 0.0, 0.0, 0.0), dir_right=(0.0, 0.0, 0.0, 0.0)) -> Params:
+                ks=0.0, dir_left=(0.0, 0.0, 0.0, 0.0), dir_right=(0.0, 0.0, 0.0, 0.0),
+                solver=SOLVER_ADOT) -> Params:
+    """``precision`` "fp64" | "mixed" (or the code); ``solver`` SOLVER_ADOT | SOLVER_DOT
+    (or "adot" | "dot")."""
     p = Params()
     p.g = g
     p.porosity = porosity
@@ -164,6 +170,7 @@ def make_params(g=9.81, porosity=0.4, A_g=0.01, n_gauss=3, cfl=0.9, dx=1.0,
     for k in range(4):
         p.dir_left[k] = float(dir_left[k])
         p.dir_right[k] = float(dir_right[k])
+    p.solver = {"adot": SOLVER_ADOT, "dot": SOLVER_DOT}[solver] if isinstance(solver, str) else int(solver)
     return p
 
 
@@ -230,7 +237,7 @@ class Context:
         return cls(h, int(off[-1]), C, True)
 
     @classmethod
-    def from_workload(cls, wl, precision=None, stream=None) -> "Context":
+    def from_workload(cls, wl, precision=None, stream=None, solver="adot") -> "Context":
         """Context for an ``inputs.Workload`` (single channel when it has one channel)."""
         prec = precision or wl.precision
         if wl.n_channels == 1:
@@ -241,11 +248,12 @@ class Context:
                               precision=prec, law=wl.law, law_extra=tuple(wl.law_par[0]),
                               h_in=float(wl.h_in[0]), h_out=float(wl.h_out[0]),
                               ks=float(wl.ks[0]), dir_left=tuple(wl.dir_left[0]),
-                              dir_right=tuple(wl.dir_right[0]))
+                              dir_right=tuple(wl.dir_right[0]), solver=solver)
         return cls.batch(wl.offsets, wl.Ag, wl.porosity, wl.dx, wl.bc_left, wl.bc_right, wl.q_in,
                          stream=stream, h_in=wl.h_in, h_out=wl.h_out, ks=wl.ks,
                          law_extra=wl.law_par, dir_left=wl.dir_left, dir_right=wl.dir_right,
-                         g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl, precision=prec, law=wl.law)
+                         g=wl.g, n_gauss=wl.n_gauss, cfl=wl.cfl, precision=prec, law=wl.law,
+                         solver=solver)
 
     # -- helpers ----------------------------------------------------------
     def _check(self, st: int, what: str):

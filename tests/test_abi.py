@@ -77,6 +77,10 @@ def test_argument_errors_without_device_work():
     for kw in bad:
         p = dsve.make_params(dx=0.1, **kw)
         assert dsve.lib.dsve_init(ctypes.byref(h), ctypes.byref(p), 10, None) == dsve.E_ARG, kw
+    p = dsve.make_params(dx=0.1, precision="mixed", solver="dot")
+    assert dsve.lib.dsve_init(ctypes.byref(h), ctypes.byref(p), 10, None) == dsve.E_UNSUPPORTED
+    p = dsve.make_params(dx=0.1, solver=2)
+    assert dsve.lib.dsve_init(ctypes.byref(h), ctypes.byref(p), 10, None) == dsve.E_ARG
     chans = dsve.make_channels([0.01, 0.01], [0.4, 0.4], [0.1, 0.1], [0, 3], [0, 0])
     off = (ctypes.c_int64 * 3)(0, 5, 10)
     p = dsve.make_params()
