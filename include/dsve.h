@@ -229,7 +229,7 @@ const char *dsve_last_error(const dsve_ctx *ctx);
 dsve_status dsve_clear_error(dsve_ctx *ctx);
 
 /* Launch configuration of the fused step kernel.
- *   tile           threads (= edges) per workgroup: 64, 128 or 256
+ *   tile           threads (= edges) per workgroup: 64, 128, 192 or 256
  *   blocks_per_cu  persistent workgroups per compute unit (1..32); 0 = as many
  *                  as fit on a compute unit at once (occupancy of the kernel)
  *   graph_steps    steps per captured HIP graph: a multiple of 6 in [6, 600],
@@ -240,10 +240,11 @@ dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int grap
 dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, int *graph_steps);
 
 /* Autotuner: time candidate (tile, blocks_per_cu) pairs for `trial_steps`
- * fused steps each on a scratch copy of (h, q, z) -- the caller's arrays are
- * read, never written -- and keep the fastest in the context.  If cache_path is
- * not NULL, a JSON cache keyed by device, precision and problem shape is read
- * first and updated after tuning.  Waits for completion. */
+ * fused steps each (rounded up to whole replays of the context's graph, after one
+ * warm-up replay that captures it) on a scratch copy of (h, q, z) -- the caller's
+ * arrays are read, never written -- and keep the fastest in the context.  If
+ * cache_path is not NULL, a JSON cache keyed by device, precision, law and problem
+ * shape is read first and updated after tuning.  Waits for completion. */
 dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
                           int trial_steps, const char *cache_path);
 

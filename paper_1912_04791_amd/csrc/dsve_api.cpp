@@ -664,8 +664,8 @@ dsve_status dsve_sync(dsve_ctx *ctx)
 dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int graph_steps)
 {
     if (!ctx) return DSVE_E_ARG;
-    if (tile < 64 || tile > kMaxTile || (tile & (tile - 1)))
-        return fail(ctx, DSVE_E_ARG, "tile must be 64, 128 or 256");
+    if (tile < 64 || tile > kMaxTile || (tile % 64))
+        return fail(ctx, DSVE_E_ARG, "tile must be 64, 128, 192 or 256");
     if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(ctx, DSVE_E_ARG, "blocks_per_cu must be in [0, 32]");
     if (graph_steps != 0 && (graph_steps % 6 || graph_steps < 6 || graph_steps > 600))
         return fail(ctx, DSVE_E_ARG, "graph_steps must be 0 or a multiple of 6 in [6, 600]");
@@ -770,24 +770,31 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
-    const int tiles[] = {64, 128, 256};
+    // tile sizes: whole waves; 192 (191 cells per tile) gives the power-of-two channel lengths
+    // a tile count that divides more evenly over the persistent grid than 255 or 127
+    const int tiles[] = {64, 128, 192, 256};
     const int bpcs[] = {0, 1, 2, 3, 4, 6, 8};
+    // Candidates run the way a run will: replays of the context's graph length when it has
+    // one (a warm-up run captures the graph, the timed run replays it), direct launches if not.
     const int save_graph = ctx->graph_steps;
+    const int warm = save_graph > 0 ? save_graph : 2;
+    const int timed = save_graph > 0 ? std::max(save_graph, (trial_steps + save_graph - 1) / save_graph * save_graph)
+                                     : trial_steps;
     float best = 1e30f;
     int best_tile = ctx->tile, best_bpc = ctx->blocks_per_cu;
     dsve_status status = DSVE_OK;
     for (int ti : tiles) {
         for (int bi : bpcs) {
-            status = dsve_set_launch(ctx, ti, bi, 0);
+            status = dsve_set_launch(ctx, ti, bi, save_graph);
             if (status != DSVE_OK) break;
             (void)hipMemcpyAsync(sh, h, bytes, hipMemcpyDeviceToDevice, ctx->stream);
             (void)hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, ctx->stream);
             (void)hipMemcpyAsync(sz, z, bytes, hipMemcpyDeviceToDevice, ctx->stream);
             (void)launch_fill_u64(reinterpret_cast<unsigned long long *>(st_), ctx->n_channels, 0ull, ctx->stream);
-            status = run_steps(ctx, sh, sq, sz, 2, st_);   // warm-up
+            status = run_steps(ctx, sh, sq, sz, warm, st_);   // warm-up (and capture)
             if (status != DSVE_OK) break;
             (void)hipEventRecord(e0, ctx->stream);
-            status = run_steps(ctx, sh, sq, sz, trial_steps, st_);
+            status = run_steps(ctx, sh, sq, sz, timed, st_);
             if (status != DSVE_OK) break;
             (void)hipEventRecord(e1, ctx->stream);
             (void)hipEventSynchronize(e1);
@@ -811,6 +818,6 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     if (status != DSVE_OK) return status;
     dsve_status st = dsve_set_launch(ctx, best_tile, best_bpc, save_graph);
     if (st != DSVE_OK) return st;
-    cache_store(cache_path, key, best_tile, best_bpc, best / trial_steps);
+    cache_store(cache_path, key, best_tile, best_bpc, best / timed);
     return DSVE_OK;
 }

@@ -112,30 +112,72 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
     unsigned long long reg_acc = 0ull;        // used by thread 0 only
     int reg_chan = -1;
 
-    for (int64_t k = blockIdx.x; k < A.n_tiles; k += gridDim.x) {
-        const int home = A.tile_chan[k];
+    // Software pipeline over the tiles of this workgroup: the channel of the tile two ahead and
+    // the edge offsets, first cell, length, boundary codes and CFL maximum of the next tile's
+    // home channel are loaded while the current tile computes, so a tile waits on one load
+    // (its state, with its channel record alongside) before it computes.  Lanes past the home
+    // channel's end find their channel by a forward scan and load its values directly.
+    const int64_t stride = gridDim.x;
+    int64_t k = blockIdx.x;
+    // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
+    int nx_home = k < A.n_tiles ? A.tile_chan[k] : 0;
+    int nx2_home = k + stride < A.n_tiles ? A.tile_chan[k + stride] : 0;
+    int64_t nx_eo0 = A.eoff[nx_home], nx_eo1 = A.eoff[nx_home + 1];
+    int nx_bcl = A.ch[nx_home].bcl, nx_bcr = A.ch[nx_home].bcr;
+    unsigned long long nx_am = A.amax_cur[nx_home];
+    for (; k < A.n_tiles; k += stride) {
+        const int home = nx_home;
+        const int64_t eo0 = nx_eo0, eo1 = nx_eo1;
+        const int64_t h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
+        const int h_bcl = nx_bcl, h_bcr = nx_bcr;
+        const unsigned long long am_home = nx_am;
         if (t == 0) s_acc = 0ull;
         const int64_t ge = k * (int64_t)(T - 1) + t;
         const bool have_edge = ge < A.n_edges;
         int c = home;
-        if (have_edge)
+        int64_t eoc = eo0, cell0 = h_cell0, ncell = h_ncell;
+        int bcl = h_bcl, bcr = h_bcr;
+        if (have_edge && ge >= eo1) {
+            c = home + 1;
             while (ge >= A.eoff[c + 1]) ++c;
+            eoc = A.eoff[c];
+            cell0 = eoc - c;
+            ncell = A.eoff[c + 1] - eoc - 1;
+            bcl = A.ch[c].bcl;
+            bcr = A.ch[c].bcr;
+        }
         const ChanInfo ci = A.ch[c];
         const Closure K = closure_of(ci);
-        const int64_t e = ge - A.eoff[c];
+        const int64_t e = ge - eoc;
         bool bad = false;
         double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
         double hR = 0.0, qR = 0.0, zR = 0.0;
+        double hL = 0.0, qL = 0.0, zL = 0.0;
+        const int64_t N = ncell, base = cell0;
         if (have_edge) {
-            const int64_t N = ci.ncell, base = ci.cell0;
-            const int64_t il = (e == 0) ? (ci.bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
-            const int64_t ir = (e == N) ? (ci.bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
-            double hL = A.h[il];
-            double qL = A.q[il];
-            double zL = A.z[il];
+            const int64_t il = (e == 0) ? (bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
+            const int64_t ir = (e == N) ? (bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
+            hL = A.h[il];
+            qL = A.q[il];
+            zL = A.z[il];
             hR = A.h[ir];
             qR = A.q[ir];
             zR = A.z[ir];
+        }
+        // the next tile's lookups go out after this tile's state loads and before its
+        // arithmetic, so waiting for the state does not wait for them
+        __builtin_amdgcn_sched_barrier(0);
+        if (k + stride < A.n_tiles) {
+            nx_home = nx2_home;
+            nx2_home = k + 2 * stride < A.n_tiles ? A.tile_chan[k + 2 * stride] : 0;
+            nx_eo0 = A.eoff[nx_home];
+            nx_eo1 = A.eoff[nx_home + 1];
+            nx_bcl = A.ch[nx_home].bcl;
+            nx_bcr = A.ch[nx_home].bcr;
+            nx_am = A.amax_cur[nx_home];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (have_edge) {
             double hRe = hR, qRe = qR, zRe = zR;
             if (e == 0) {
                 hL = ghost_h(ci.bcl, ci.bl, hL);
@@ -152,13 +194,13 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         s_dm[T + t] = Dm[1];
         s_dm[2 * T + t] = Dm[2];
         __syncthreads();
-        const bool upd = have_edge && (t < T - 1) && (e < ci.ncell);
+        const bool upd = have_edge && (t < T - 1) && (e < ncell);
         unsigned long long sp_bits = 0ull;
         if (upd) {
-            const double amax = __longlong_as_double((long long)A.amax_cur[c]);
+            const double amax = __longlong_as_double((long long)(c == home ? am_home : A.amax_cur[c]));
             const double dt = ci.cfl_dx * rcp_h(amax);
             const double r = dt * ci.inv_dx;
-            const int64_t i = ci.cell0 + e;
+            const int64_t i = cell0 + e;
             // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i^n)
             // (Sec. 3, Eq. scheme; S from the friction slope when K_s is given)
             const double hn = hR - r * (s_dm[t + 1] + Dp[0]);

@@ -171,7 +171,7 @@ def test_single_cell_channels_batched(torch_dev, dsve):
 def test_launch_configuration_does_not_change_bits(torch_dev, dsve):
     wl = inputs.make_c4(n_channels=12, len_lo=100, len_hi=5000, steps=37)
     outs = []
-    for launch in [(256, 0, 60), (64, 1, 0), (128, 2, 6), (256, 4, 12), (64, 8, 36)]:
+    for launch in [(256, 0, 60), (64, 1, 0), (128, 2, 6), (256, 4, 12), (64, 8, 36), (192, 2, 18)]:
         outs.append(run_gpu(dsve, torch_dev, wl, launch=launch))
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):

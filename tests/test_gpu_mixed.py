@@ -123,7 +123,7 @@ def test_full_size_c3_two_steps_mixed(torch_dev, dsve):
 
 def test_mixed_is_deterministic_across_launches(torch_dev, dsve):
     wl = inputs.make_c5(n_channels=20, len_lo=512, len_hi=2048, steps=25)
-    outs = [run_gpu(dsve, wl, launch=l) for l in [(256, 0, 0), (64, 4, 12), (128, 1, 24)]]
+    outs = [run_gpu(dsve, wl, launch=l) for l in [(256, 0, 0), (64, 4, 12), (128, 1, 24), (192, 3, 6)]]
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
