@@ -103,7 +103,10 @@ __device__ __forceinline__ double ghost_z(int bc, const double *b, double z, dou
 
 // ---------------------------------------------------------------------------
 template <int G, int PREC, int CL>
-__global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(StepArgs A)
+__global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(StepArgs A, const ChanInfo *__restrict__ CH,
+                                                                           const int64_t *__restrict__ EO,
+                                                                           const int32_t *__restrict__ TC,
+                                                                           const unsigned long long *__restrict__ AM)
 {
     extern __shared__ double s_dm[];          // [3][T]
     __shared__ unsigned long long s_acc;
@@ -120,11 +123,11 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
     const int64_t stride = gridDim.x;
     int64_t k = blockIdx.x;
     // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
-    int nx_home = k < A.n_tiles ? A.tile_chan[k] : 0;
-    int nx2_home = k + stride < A.n_tiles ? A.tile_chan[k + stride] : 0;
-    int64_t nx_eo0 = A.eoff[nx_home], nx_eo1 = A.eoff[nx_home + 1];
-    int nx_bcl = A.ch[nx_home].bcl, nx_bcr = A.ch[nx_home].bcr;
-    unsigned long long nx_am = A.amax_cur[nx_home];
+    int nx_home = k < A.n_tiles ? TC[k] : 0;
+    int nx2_home = k + stride < A.n_tiles ? TC[k + stride] : 0;
+    int64_t nx_eo0 = EO[nx_home], nx_eo1 = EO[nx_home + 1];
+    int nx_bcl = CH[nx_home].bcl, nx_bcr = CH[nx_home].bcr;
+    unsigned long long nx_am = AM[nx_home];
     for (; k < A.n_tiles; k += stride) {
         const int home = nx_home;
         const int64_t eo0 = nx_eo0, eo1 = nx_eo1;
@@ -139,14 +142,18 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         int bcl = h_bcl, bcr = h_bcr;
         if (have_edge && ge >= eo1) {
             c = home + 1;
-            while (ge >= A.eoff[c + 1]) ++c;
-            eoc = A.eoff[c];
+            while (ge >= EO[c + 1]) ++c;
+            eoc = EO[c];
             cell0 = eoc - c;
-            ncell = A.eoff[c + 1] - eoc - 1;
-            bcl = A.ch[c].bcl;
-            bcr = A.ch[c].bcr;
+            ncell = EO[c + 1] - eoc - 1;
+            bcl = CH[c].bcl;
+            bcr = CH[c].bcr;
         }
-        const ChanInfo ci = A.ch[c];
+        // the home channel's record is the same for the whole workgroup (scalar loads); lanes
+        // of another channel load their own
+        const ChanInfo hci = CH[home];
+        ChanInfo ci = hci;
+        if (c != home) ci = CH[c];
         const Closure K = closure_of(ci);
         const int64_t e = ge - eoc;
         bool bad = false;
@@ -169,12 +176,12 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         __builtin_amdgcn_sched_barrier(0);
         if (k + stride < A.n_tiles) {
             nx_home = nx2_home;
-            nx2_home = k + 2 * stride < A.n_tiles ? A.tile_chan[k + 2 * stride] : 0;
-            nx_eo0 = A.eoff[nx_home];
-            nx_eo1 = A.eoff[nx_home + 1];
-            nx_bcl = A.ch[nx_home].bcl;
-            nx_bcr = A.ch[nx_home].bcr;
-            nx_am = A.amax_cur[nx_home];
+            nx2_home = k + 2 * stride < A.n_tiles ? TC[k + 2 * stride] : 0;
+            nx_eo0 = EO[nx_home];
+            nx_eo1 = EO[nx_home + 1];
+            nx_bcl = CH[nx_home].bcl;
+            nx_bcr = CH[nx_home].bcr;
+            nx_am = AM[nx_home];
         }
         __builtin_amdgcn_sched_barrier(0);
         if (have_edge) {
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const bool upd = have_edge && (t < T - 1) && (e < ncell);
         unsigned long long sp_bits = 0ull;
         if (upd) {
-            const double amax = __longlong_as_double((long long)(c == home ? am_home : A.amax_cur[c]));
+            const double amax = __longlong_as_double((long long)(c == home ? am_home : AM[c]));
             const double dt = ci.cfl_dx * rcp_h(amax);
             const double r = dt * ci.inv_dx;
             const int64_t i = cell0 + e;
@@ -383,7 +390,8 @@ template <int PREC>
 static hipError_t launch_step_prec(const StepArgs &a, int G, int cl, int tile, int grid, hipStream_t s)
 {
     const size_t lds = sizeof(double) * 3 * (size_t)tile;
-#define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC>), dim3(grid), dim3(tile), lds, s, a)
+#define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC>), dim3(grid), dim3(tile), lds, s, a, \
+                                                   a.ch, a.eoff, a.tile_chan, a.amax_cur)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_STEP)
 #undef DSVE_LAUNCH_STEP
     return hipGetLastError();
