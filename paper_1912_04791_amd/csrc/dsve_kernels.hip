@@ -60,6 +60,18 @@ __device__ __forceinline__ void reduce_channel_max(unsigned long long v, int cha
     }
 }
 
+// Atomic maximum of a workgroup's partial result into a per-channel slot, skipped when the slot
+// already holds at least the value.  Slot values only grow while a kernel runs, so a load that
+// returns an older (smaller) value only costs an atomic that was not needed; the load bypasses
+// the compute unit's cache.  Most workgroups do not hold their channel's maximum, so most
+// flushes skip the atomic, which would otherwise serialise on the one address at the end of
+// the kernel.
+__device__ __forceinline__ void flush_max(unsigned long long *slot, unsigned long long v)
+{
+    const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v > cur) atomicMax(slot, v);
+}
+
 __device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
 {
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1u);
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         __syncthreads();
         if (t == 0) {
             if (home != reg_chan) {
-                if (reg_chan >= 0) atomicMax(&A.amax_next[reg_chan], reg_acc);
+                if (reg_chan >= 0) flush_max(&A.amax_next[reg_chan], reg_acc);
                 reg_chan = home;
                 reg_acc = s_acc;
             } else {
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             }
         }
     }
-    if (t == 0 && reg_chan >= 0) atomicMax(&A.amax_next[reg_chan], reg_acc);
+    if (t == 0 && reg_chan >= 0) flush_max(&A.amax_next[reg_chan], reg_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -281,7 +293,7 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
         __syncthreads();
         if (threadIdx.x == 0) {
             if (home != reg_chan) {
-                if (reg_chan >= 0) atomicMax(&A.amax[reg_chan], reg_acc);
+                if (reg_chan >= 0) flush_max(&A.amax[reg_chan], reg_acc);
                 reg_chan = home;
                 reg_acc = s_acc;
             } else {
@@ -289,7 +301,7 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs A)
             }
         }
     }
-    if (threadIdx.x == 0 && reg_chan >= 0) atomicMax(&A.amax[reg_chan], reg_acc);
+    if (threadIdx.x == 0 && reg_chan >= 0) flush_max(&A.amax[reg_chan], reg_acc);
 }
 
 template <int G, int PREC, int CL>
