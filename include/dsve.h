@@ -230,8 +230,9 @@ dsve_status dsve_clear_error(dsve_ctx *ctx);
 
 /* Launch configuration of the fused step kernel.
  *   tile           threads (= edges) per workgroup: 64, 128, 192 or 256
- *   blocks_per_cu  persistent workgroups per compute unit (1..32); 0 = as many
- *                  as fit on a compute unit at once (occupancy of the kernel)
+ *   blocks_per_cu  persistent workgroups per compute unit (1..1024); 0 = as many
+ *                  as fit on a compute unit at once (occupancy of the kernel); more than
+ *                  fit oversubscribes the grid (workgroups start as others finish)
  *   graph_steps    steps per captured HIP graph: a multiple of 6 in [6, 600],
  *                  or 0 to launch every step directly
  * The results do not depend on these (each edge and cell is computed the same
@@ -240,8 +241,9 @@ dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int grap
 dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, int *graph_steps);
 
 /* Autotuner: time candidate (tile, blocks_per_cu) pairs for `trial_steps`
- * fused steps each (rounded up to whole replays of the context's graph, after one
- * warm-up replay that captures it) on a scratch copy of (h, q, z) -- the caller's
+ * fused steps each (rounded up to whole replays of a 12-step graph, after one warm-up
+ * replay that captures it, when the context uses graphs) on a scratch copy of (h, q, z),
+ * over tiles of 64..256 threads and 0..128 workgroups per compute unit -- the caller's
  * arrays are read, never written -- and keep the fastest in the context.  If
  * cache_path is not NULL, a JSON cache keyed by device, precision, law and problem
  * shape is read first and updated after tuning.  Waits for completion. */

@@ -666,7 +666,7 @@ dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int grap
     if (!ctx) return DSVE_E_ARG;
     if (tile < 64 || tile > kMaxTile || (tile % 64))
         return fail(ctx, DSVE_E_ARG, "tile must be 64, 128, 192 or 256");
-    if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(ctx, DSVE_E_ARG, "blocks_per_cu must be in [0, 32]");
+    if (blocks_per_cu < 0 || blocks_per_cu > 1024) return fail(ctx, DSVE_E_ARG, "blocks_per_cu must be in [0, 1024]");
     if (graph_steps != 0 && (graph_steps % 6 || graph_steps < 6 || graph_steps > 600))
         return fail(ctx, DSVE_E_ARG, "graph_steps must be 0 or a multiple of 6 in [6, 600]");
     if (tile != ctx->tile) {
@@ -773,19 +773,23 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     // tile sizes: whole waves; 192 (191 cells per tile) gives the power-of-two channel lengths
     // a tile count that divides more evenly over the persistent grid than 255 or 127
     const int tiles[] = {64, 128, 192, 256};
-    const int bpcs[] = {0, 1, 2, 3, 4, 6, 8};
-    // Candidates run the way a run will: replays of the context's graph length when it has
-    // one (a warm-up run captures the graph, the timed run replays it), direct launches if not.
+    // workgroups per compute unit: 0 = as many as are resident at once; counts above that
+    // oversubscribe the persistent grid, so the hardware hands tiles out to workgroups as
+    // others finish
+    const int bpcs[] = {0, 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128};
+    // Candidates run the way a run will: replays of a captured graph when the context uses
+    // graphs (a warm-up run captures it, the timed run replays it; 12-step graphs keep the
+    // trials short), direct launches if not.
     const int save_graph = ctx->graph_steps;
-    const int warm = save_graph > 0 ? save_graph : 2;
-    const int timed = save_graph > 0 ? std::max(save_graph, (trial_steps + save_graph - 1) / save_graph * save_graph)
-                                     : trial_steps;
+    const int tg = save_graph > 0 ? std::min(save_graph, 12) : 0;
+    const int warm = tg > 0 ? tg : 2;
+    const int timed = tg > 0 ? std::max(tg, (trial_steps + tg - 1) / tg * tg) : trial_steps;
     float best = 1e30f;
     int best_tile = ctx->tile, best_bpc = ctx->blocks_per_cu;
     dsve_status status = DSVE_OK;
     for (int ti : tiles) {
         for (int bi : bpcs) {
-            status = dsve_set_launch(ctx, ti, bi, save_graph);
+            status = dsve_set_launch(ctx, ti, bi, tg);
             if (status != DSVE_OK) break;
             (void)hipMemcpyAsync(sh, h, bytes, hipMemcpyDeviceToDevice, ctx->stream);
             (void)hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, ctx->stream);

@@ -171,7 +171,7 @@ def test_single_cell_channels_batched(torch_dev, dsve):
 def test_launch_configuration_does_not_change_bits(torch_dev, dsve):
     wl = inputs.make_c4(n_channels=12, len_lo=100, len_hi=5000, steps=37)
     outs = []
-    for launch in [(256, 0, 60), (64, 1, 0), (128, 2, 6), (256, 4, 12), (64, 8, 36), (192, 2, 18)]:
+    for launch in [(256, 0, 60), (64, 1, 0), (128, 2, 6), (256, 4, 12), (64, 8, 36), (192, 2, 18), (64, 128, 6)]:
         outs.append(run_gpu(dsve, torch_dev, wl, launch=launch))
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
@@ -248,7 +248,7 @@ def test_nonfinite_state_is_reported(torch_dev, dsve):
 def test_bad_launch_arguments(torch_dev, dsve):
     wl = inputs.make_c1()
     ctx = dsve.Context.from_workload(wl)
-    for bad in [(96, 0, 60), (512, 0, 60), (256, -1, 60), (256, 33, 60), (256, 0, 7)]:
+    for bad in [(96, 0, 60), (512, 0, 60), (256, -1, 60), (256, 1025, 60), (256, 0, 7)]:
         with pytest.raises(dsve.DsveError):
             ctx.set_launch(*bad)
         ctx.clear_error()
