@@ -30,11 +30,13 @@ def dsve():
     return d
 
 
-def run_gpu(dsve, wl, steps=None, precision="mixed", launch=None):
+def run_gpu(dsve, wl, steps=None, precision="mixed", launch=None, autotune=False):
     ctx = dsve.Context.from_workload(wl, precision=precision)
     if launch is not None:
         ctx.set_launch(*launch)
     h, q, z, t = dsve.upload(wl)
+    if autotune:   # the launch the benchmark times: tuned on a scratch copy of the state
+        ctx.autotune(h, q, z, trial_steps=20)
     ctx.adot_step(h, q, z, wl.steps if steps is None else steps, t)
     ctx.sync()
     out = (h.cpu().numpy(), q.cpu().numpy(), z.cpu().numpy(), t.cpu().numpy())
@@ -116,8 +118,15 @@ def test_c5_shape_batched_reduced(torch_dev, dsve):
 
 def test_full_size_c3_two_steps_mixed(torch_dev, dsve):
     wl = inputs.make_c3()
-    got = run_gpu(dsve, wl, steps=2)
+    got = run_gpu(dsve, wl, steps=2, autotune=True)
     ref = oracle_run(wl, steps=2)
+    assert max_rel_l1(got, ref) <= TOL
+
+
+def test_full_size_c2_mixed_autotuned_launch(torch_dev, dsve):
+    wl = inputs.make_c2()
+    got = run_gpu(dsve, wl, steps=66, autotune=True)
+    ref = oracle_run(wl, steps=66)
     assert max_rel_l1(got, ref) <= TOL
 
 
