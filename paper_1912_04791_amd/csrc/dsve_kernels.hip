@@ -27,14 +27,30 @@
 
 namespace dsve {
 
+// Maximum over the 64 lanes of a wave, in lane 63, read back to every lane.  DPP lane moves
+// on the two 32-bit halves: swaps within quads, half-row and row mirrors (each lane then holds
+// its row of 16), then the broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows 2
+// and 3.  Lanes whose DPP source is out of range keep their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_umax(unsigned long long v)
+{
+    const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+    return (o > v) ? o : v;
+}
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off, 64);
-        v = (o > v) ? o : v;
-    }
-    return v;
+    v = dpp_umax<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_umax<0x4E, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_umax<0x141, 0xf>(v);   // row_half_mirror
+    v = dpp_umax<0x140, 0xf>(v);   // row_mirror
+    v = dpp_umax<0x142, 0xa>(v);   // row_bcast:15
+    v = dpp_umax<0x143, 0xc>(v);   // row_bcast:31
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Per-channel maximum of `v` (bit patterns of non-negative doubles, so unsigned order is

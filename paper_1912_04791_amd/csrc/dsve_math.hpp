@@ -44,8 +44,16 @@
 //     point on the unit circle, renormalised in FP64; the residual angle follows from the
 //     complex identity Im(w conj(z)^3) = sin(phi - 3 theta0), w = x + i sqrt(1 - x^2),
 //     z = cos(theta0) + i sin(theta0), and a rotation by residual/3 (second-order sine and
-//     cosine of a small angle) removes it; each correction leaves an error of order
-//     (residual)^3.
+//     cosine of a small angle) removes it, leaving an error of order (residual)^3.  The
+//     estimate is arccos(a) = sqrt(1 - a) P(a), a = |x|, with 1 - a formed in FP64 (so the
+//     square-root behaviour at |x| -> 1 keeps its relative accuracy) and P of degree 5
+//     fitted by least squares on Chebyshev nodes of [0, 1]; its error stays below 1.4e-6
+//     in FP32 arithmetic, which one correction takes below FP64 rounding.
+//   Gap product: (mu_2 - mu_1)(mu_3 - mu_1)(mu_3 - mu_2) = (3 sqrt3 / 4) m^3 sin(3 theta)
+//     = (2 sqrt3 / 9) k1^(3/2) sin(phi), so its reciprocal is (3 sqrt3 / 2) k1^(-3/2) / sin(phi),
+//     from the k1^(-1/2) and 1/sin(phi) the roots already need.
+//   In the mixed form the FP32 arccos is the degree-7 approximation of Abramowitz & Stegun
+//     (Handbook, 4.4.46; error below 2e-8).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,7 +66,7 @@ namespace dsve {
 
 constexpr double kSqrt3Half = 0.86602540378443864676372317075293618;
 constexpr double kAcosTol = 1e-12;            // tolerance on |arccos argument| - 1 before flagging
-constexpr double kTrisectTwoRounds = 0.984;   // |x| above which the FP32 estimate gets two rounds
+constexpr double kInvGapScale = 2.59807621135331594029116951225880855;   // 3 sqrt3 / 2
 constexpr float kMixedFp64Band = 1e-3f;       // mixed form: 1 - |x| below this -> FP64 node
 
 // Unrolling of the quadrature-node loop (independent nodes interleave for ILP when unrolled;
@@ -100,12 +108,43 @@ __device__ __forceinline__ void trisect_correct(double x, double y, double &c, d
     s = sn;
 }
 
-// (cos theta, sin theta), theta = arccos(x) / 3, x in [-1, 1] (NaN propagates).
-__device__ __forceinline__ void trisect(double x, double &c, double &s)
+// FP32 estimate of arccos(x), x in [-1, 1], for the trisection (see the header).
+__device__ __forceinline__ float acos_seed(double x)
+{
+    const double ax = fabs(x);
+    const float a = (float)ax;
+    float p = fmaf(a, -0.004258281551301479f, 0.01915096305310726f);
+    p = fmaf(a, p, -0.044784508645534515f);
+    p = fmaf(a, p, 0.08781391382217407f);
+    p = fmaf(a, p, -0.21450453996658325f);
+    p = fmaf(a, p, 1.5707950592041016f);
+    const float r = p * __builtin_amdgcn_sqrtf((float)(1.0 - ax));
+    return x < 0.0 ? 3.14159265358979f - r : r;
+}
+
+// FP32 arccos for the mixed form (Abramowitz & Stegun 4.4.46, degree 7).
+__device__ __forceinline__ float acos_f32(float x)
+{
+    const float a = fabsf(x);
+    float p = fmaf(a, -0.0012624911f, 0.0066700901f);
+    p = fmaf(a, p, -0.0170881256f);
+    p = fmaf(a, p, 0.0308918810f);
+    p = fmaf(a, p, -0.0501743046f);
+    p = fmaf(a, p, 0.0889789874f);
+    p = fmaf(a, p, -0.2145988016f);
+    p = fmaf(a, p, 1.5707963050f);
+    const float r = p * __builtin_amdgcn_sqrtf(1.0f - a);
+    return x < 0.0f ? 3.14159265358979f - r : r;
+}
+
+// (cos theta, sin theta), theta = arccos(x) / 3, and 1 / sin(3 theta), x in [-1, 1] (NaN
+// propagates; at x = +-1 the reciprocal is huge but finite).
+__device__ __forceinline__ void trisect(double x, double &c, double &s, double &inv_y)
 {
     const double v = fma(-x, x, 1.0);
-    const double y = v * rsqrt_h(fmax(v, 1e-300));   // sin(phi); 0 at x = +-1, NaN stays NaN
-    const float th0 = acosf((float)x) * (1.0f / 3.0f);
+    inv_y = rsqrt_h(fmax(v, 1e-300));
+    const double y = v * inv_y;   // sin(phi); 0 at x = +-1, NaN stays NaN
+    const float th0 = acos_seed(x) * (1.0f / 3.0f);
     const double c0 = (double)__cosf(th0), s0 = (double)__sinf(th0);
     // renormalise: 1/sqrt(c0^2 + s0^2) to second order in e = c0^2 + s0^2 - 1 (|e| ~ 1e-7)
     const double e = fma(c0, c0, fma(s0, s0, -1.0));
@@ -113,7 +152,6 @@ __device__ __forceinline__ void trisect(double x, double &c, double &s)
     c = c0 * nr;
     s = s0 * nr;
     trisect_correct(x, y, c, s);
-    if (fabs(x) > kTrisectTwoRounds) trisect_correct(x, y, c, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,6 +241,7 @@ struct Eig64 {
     double Fr, c, inv_c, b, kFr;
     double mu1, mu2, mu3;
     double g21, g31, g32;   // mu_2 - mu_1, mu_3 - mu_1, mu_3 - mu_2
+    double inv_gp;          // 1 / (g21 g31 g32)
 };
 
 template <int CL>
@@ -216,13 +255,14 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     double k1, k2, b, kFr;
     cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
     const double r1 = rsqrt_h(k1);
-    double x = (0.5 * k2) * (r1 * r1 * r1);   // k2 / sqrt(4 k1^3)
+    const double r13 = r1 * r1 * r1;
+    double x = (0.5 * k2) * r13;   // k2 / sqrt(4 k1^3)
     // complex roots: arccos argument beyond 1 + tol or k1 <= 0 (NaN compares false: a NaN
     // state is reported as non-finite by the CFL maximum instead)
     bad |= (fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0);
     x = fmin(fmax(x, -1.0), 1.0);   // a NaN x only arises with a NaN Fr, which the roots carry
-    double cs, sn;
-    trisect(x, cs, sn);
+    double cs, sn, inv_y;
+    trisect(x, cs, sn, inv_y);
     const double m = (2.0 / 3.0) * (k1 * r1);
     const double f = (2.0 / 3.0) * Fr;
     const double p = 0.5 * cs, r = kSqrt3Half * sn;
@@ -237,6 +277,7 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     E.g21 = (2.0 * m) * r;
     E.g31 = m * fma(3.0, p, r);
     E.g32 = m * fma(3.0, p, -r);
+    E.inv_gp = (kInvGapScale * r13) * inv_y;
 }
 
 // Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).
@@ -264,7 +305,7 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
     const double n2 = fma(fma(mu3, mu1, base), dh, fma(mu2, dqn, dz));
     const double n3 = fma(fma(mu1, mu2, base), dh, fma(mu3, dqn, dz));
     // w |mu_i| (l_i . dW), denominators 1/d_1 = g32/P, 1/d_2 = -g31/P, 1/d_3 = g21/P
-    const double wP = w * rcp_h(E.g21 * E.g31 * E.g32);
+    const double wP = w * E.inv_gp;
     const double b1 = n1 * (fabs(mu1) * E.g32) * wP;
     const double b2 = -n2 * (fabs(mu2) * E.g31) * wP;
     const double b3 = n3 * (fabs(mu3) * E.g21) * wP;
@@ -327,7 +368,7 @@ __device__ __forceinline__ bool eigf(float h, float q, float g, const Closure &K
     const float r1 = __builtin_amdgcn_rsqf(k1);
     float x = (0.5f * k2) * (r1 * r1 * r1);
     if (!(fabsf(x) < 1.0f - kMixedFp64Band)) return false;
-    const float th = acosf(x) * (1.0f / 3.0f);
+    const float th = acos_f32(x) * (1.0f / 3.0f);
     const float cs = __cosf(th), sn = __sinf(th);
     const float m = (2.0f / 3.0f) * (k1 * r1);
     const float f = (2.0f / 3.0f) * Fr;

@@ -1,0 +1,99 @@
+"""Accuracy of the FP32 arccos approximations the device code uses (host-side checks of the
+coefficients in dsve_math.hpp, evaluated in FP32 as the kernels evaluate them).
+
+The FP64 trisection takes an FP32 estimate of arccos(x) and corrects it once; the correction
+leaves an error of order (estimate error / 3)^3, so an estimate good to a few 1e-6 is enough.
+The mixed form uses its FP32 arccos directly, so it must be as good as a library FP32 arccos.
+"""
+import os
+import re
+
+import numpy as np
+
+HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1912_04791_amd", "csrc", "dsve_math.hpp")
+
+
+def _coeffs(fn):
+    """Horner coefficients (highest degree first) and the reflection constant pi of `fn`."""
+    src = open(HDR).read()
+    body = src[src.index(f"float {fn}("):]
+    body = body[:body.index("\n}\n")]
+    lit = r"(-?\d+\.\d+(?:e-?\d+)?)f"
+    first = re.search(r"fmaf\(a, " + lit + ", " + lit + r"\)", body)
+    rest = re.findall(r"fmaf\(a, p, " + lit + r"\)", body)
+    pi_f = float(re.search(r"\? " + lit + " - r", body).group(1))
+    return [float(first.group(1)), float(first.group(2))] + [float(v) for v in rest], pi_f
+
+
+def _horner_f32(cs, a):
+    p = np.float32(cs[0])
+    for c in cs[1:]:
+        p = (a * p + np.float32(c)).astype(np.float32)
+    return p
+
+
+def _estimate(fn, x64, one_minus_in_fp64):
+    cs, pi_f = _coeffs(fn)
+    ax = np.abs(x64)
+    a = ax.astype(np.float32)
+    p = _horner_f32(cs, a)
+    om = (1.0 - ax).astype(np.float32) if one_minus_in_fp64 else (np.float32(1) - a)
+    r = (p * np.sqrt(om)).astype(np.float32)
+    return np.where(x64 < 0, np.float32(pi_f) - r, r).astype(np.float64)
+
+
+def _grid():
+    near = np.logspace(-16, -1, 4000)
+    return np.concatenate([np.linspace(-1.0, 1.0, 400001), 1 - near, -1 + near])
+
+
+def test_trisection_seed_error_bound():
+    x = _grid()
+    err = np.abs(_estimate("acos_seed", x, True) - np.arccos(x))
+    assert err.max() < 1.5e-6, err.max()
+
+
+def test_trisection_seed_then_one_correction_reaches_fp64():
+    # one correction of the trisection from the estimate (FP32 cosine and sine of theta0/3),
+    # as in the kernels: the result agrees with cos/sin(arccos(x)/3) to a few ulp
+    x = _grid()
+    th0 = (_estimate("acos_seed", x, True).astype(np.float32) * np.float32(1 / 3)).astype(np.float32)
+    c = np.cos(th0).astype(np.float32).astype(np.float64)
+    s = np.sin(th0).astype(np.float32).astype(np.float64)
+    e = c * c + s * s - 1
+    nr = 1 + e * (-0.5 + 0.375 * e)
+    c, s = c * nr, s * nr
+    y = np.sqrt(np.maximum((1 - x) * (1 + x), 0))
+    C3, S3 = c * (4 * c * c - 3), s * (3 - 4 * s * s)
+    d = (y * C3 - x * S3) / 3
+    cd = 1 - 0.5 * d * d
+    c, s = c * cd - s * d, s * cd + c * d
+    th = np.arccos(x) / 3
+    assert np.abs(c - np.cos(th)).max() < 2e-15
+    assert np.abs(s - np.sin(th)).max() < 2e-15
+
+
+def test_mixed_form_arccos_matches_an_fp32_library_arccos():
+    x = np.linspace(-1.0, 1.0, 400001).astype(np.float32).astype(np.float64)
+    ours = np.abs(_estimate("acos_f32", x, False) - np.arccos(x)).max()
+    lib = np.abs(np.arccos(x.astype(np.float32)).astype(np.float64) - np.arccos(x)).max()
+    assert ours < 5e-7 and ours < 1.5 * lib, (ours, lib)
+
+
+def test_gap_product_identity():
+    # (mu2 - mu1)(mu3 - mu1)(mu3 - mu2) = (2 sqrt3 / 9) k1^(3/2) sin(phi) for the roots
+    # mu = f - m cos(theta -+ pi/3), f + m cos(theta), m = (2/3) sqrt(k1), 3 theta = phi
+    rng = np.random.default_rng(5)
+    k1 = rng.uniform(0.1, 20.0, 1000)
+    phi = rng.uniform(0.0, np.pi, 1000)
+    f = rng.uniform(-2, 2, 1000)
+    m = 2.0 / 3.0 * np.sqrt(k1)
+    th = phi / 3
+    mu1 = f - m * np.cos(th - np.pi / 3)
+    mu2 = f - m * np.cos(th + np.pi / 3)
+    mu3 = f + m * np.cos(th)
+    P = (mu2 - mu1) * (mu3 - mu1) * (mu3 - mu2)
+    np.testing.assert_allclose(P, 2 * np.sqrt(3) / 9 * k1 ** 1.5 * np.sin(phi), rtol=1e-9, atol=1e-12)
+    src = open(HDR).read()
+    val = float(re.search(r"kInvGapScale = ([0-9.]+);", src).group(1))
+    assert abs(val - 1.5 * np.sqrt(3)) < 1e-15
