@@ -90,7 +90,8 @@ def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: s
     stream = torch.cuda.current_stream()
     ctx = dsve.Context.from_workload(wl, precision=precision, stream=stream, solver=solver)
     if launch:
-        ctx.set_launch(*launch)
+        ctx.set_launch(*launch[:3])
+        ctx.set_cfl_split(launch[3])
     h, q, z, t = dsve.upload(wl)
     if launch is None:
         # pick tile and persistent grid size on a scratch copy (outside the timed region)
@@ -109,7 +110,8 @@ def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: s
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1)
-    res = {"ms_total": ms, "wall_s": wall, "launch": ctx.get_launch(), "cus": ctx.device_cus()}
+    res = {"ms_total": ms, "wall_s": wall, "launch": (*ctx.get_launch(), ctx.get_cfl_split()),
+           "cus": ctx.device_cus()}
     ctx.close()
     return res
 
@@ -201,6 +203,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=-1)
+    ap.add_argument("--cfl-split", type=int, default=0,
+                    help="CFL sub-slots per channel with an explicit launch (0 = automatic)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
@@ -234,7 +238,7 @@ def main():
     launch = None
     if args.tile or args.blocks_per_cu >= 0 or args.graph_steps >= 0:
         launch = (args.tile or 256, max(args.blocks_per_cu, 0),
-                  60 if args.graph_steps < 0 else args.graph_steps)
+                  60 if args.graph_steps < 0 else args.graph_steps, args.cfl_split)
 
     if args.precisions is None:
         args.precisions = "mixed,fp64" if wl.precision == "mixed" else "fp64,mixed"
@@ -273,7 +277,8 @@ def main():
                    "n_cells": wl.n_cells, "n_channels": wl.n_channels,
                    "edges_per_step": edges, "precision": main_prec,
                    "launch": {"tile": main["launch"][0], "blocks_per_cu": main["launch"][1],
-                              "graph_steps": main["launch"][2]},
+                              "graph_steps": main["launch"][2],
+                              "cfl_split": main["launch"][3]},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved_tflops / peak,
@@ -291,7 +296,7 @@ def main():
         out[prec] = {"value": r["edge_updates_per_s"], "ms_per_step": r["ms_per_step"],
                      "speedup_vs_" + main_prec: r["edge_updates_per_s"] / main["edge_updates_per_s"],
                      "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
-                                "graph_steps": r["launch"][2]},
+                                "graph_steps": r["launch"][2], "cfl_split": r["launch"][3]},
                      "roofline": {"bound": "alu", "achieved": achieved_p, "peak": peak_p,
                                   "unit": "TFLOP/s", "frac": achieved_p / peak_p,
                                   "traffic": measured_traffic(wl.name, prec)}}
@@ -306,7 +311,7 @@ def main():
         out["dot_fp64"] = {"value": v, "ms_per_step": r["ms_total"] / args.dot_steps,
                            "steps": args.dot_steps,
                            "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
-                                      "graph_steps": r["launch"][2]},
+                                      "graph_steps": r["launch"][2], "cfl_split": r["launch"][3]},
                            "adot_fp64_speedup": (adot64["edge_updates_per_s"] / v) if adot64 else None}
 
     if not args.no_cpu:

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DSVE_ABI_VERSION 2
+#define DSVE_ABI_VERSION 3
 
 typedef struct dsve_ctx dsve_ctx;
 
@@ -240,13 +240,24 @@ dsve_status dsve_clear_error(dsve_ctx *ctx);
 dsve_status dsve_set_launch(dsve_ctx *ctx, int tile, int blocks_per_cu, int graph_steps);
 dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, int *graph_steps);
 
+/* CFL sub-slots of the fused step kernel: each workgroup merges its partial
+ * CFL maximum with an atomic into one of `split` sub-slots per channel (1, 2 or
+ * 4; 0, the default, picks 4 when many workgroups share a channel and each
+ * merges after a few tiles, else 1), and every tile reads the maximum over them.
+ * More sub-slots spread the atomics of a step over more addresses; fewer keep
+ * the read to fewer loads.  The results do not depend on it.  The getter reports
+ * the count in effect for the current launch configuration. */
+dsve_status dsve_set_cfl_split(dsve_ctx *ctx, int split);
+dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split);
+
 /* Autotuner: time candidate (tile, blocks_per_cu) pairs for `trial_steps`
  * fused steps each (rounded up to whole replays of a 12-step graph, after one warm-up
  * replay that captures it, when the context uses graphs) on a scratch copy of (h, q, z),
- * over tiles of 64..256 threads and 0..128 workgroups per compute unit -- the caller's
- * arrays are read, never written -- and keep the fastest in the context.  If
- * cache_path is not NULL, a JSON cache keyed by device, precision, law and problem
- * shape is read first and updated after tuning.  Waits for completion. */
+ * over tiles of 64..256 threads and 0..128 workgroups per compute unit, then the three
+ * fastest with 1 and with 4 CFL sub-slots -- the caller's arrays are read, never written
+ * -- and keep the fastest in the context.  If cache_path is not NULL, a JSON cache keyed
+ * by device, precision, law and problem shape is read first and updated after tuning.
+ * Waits for completion. */
 dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
                           int trial_steps, const char *cache_path);
 

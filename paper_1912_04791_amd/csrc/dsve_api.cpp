@@ -44,11 +44,13 @@ struct dsve_ctx {
     std::vector<int64_t> h_off, h_eoff;
     ChanInfo *d_ch = nullptr;
     int64_t *d_off = nullptr, *d_eoff = nullptr;
-    GaussRule rule{};
 
     double *pp_h = nullptr, *pp_q = nullptr, *pp_z = nullptr;   // ping-pong copy
     double *pp_t = nullptr;                                      // ping-pong clocks [C]
-    unsigned long long *d_amax = nullptr;                        // [3][C]
+    unsigned long long *d_amax = nullptr;                        // [3][S][Cs]
+    int64_t amax_cs = 0;                                         // Cs (sub-slot stride)
+    int64_t amax_slot = 0;                                       // kAmaxSplitMax * Cs (one slot)
+    int cfl_split = 0;                                           // CFL sub-slots; 0 = automatic
     unsigned int *d_flags = nullptr;                             // [4]
 
     int tile = 256, blocks_per_cu = 0, graph_steps = 60;
@@ -58,7 +60,7 @@ struct dsve_ctx {
 
     hipGraphExec_t gexec = nullptr;
     const void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
-    int g_steps = 0, g_tile = 0, g_grid = 0;
+    int g_steps = 0, g_tile = 0, g_grid = 0, g_split = 0;
 
     int last_amax_slot = -1;   // slot holding the CFL max of the latest state, or -1
     dsve_status sticky = DSVE_OK;
@@ -81,44 +83,6 @@ static dsve_status fail(dsve_ctx *c, dsve_status st, const std::string &msg)
         if (e__ != hipSuccess)                                                               \
             return fail((ctx), DSVE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
     } while (0)
-
-// Gauss-Legendre rules on [0, 1] from the closed forms of the Legendre roots for G <= 5
-// (nodes x in [-1, 1] mapped by s = (1 + x)/2, weights halved so they sum to one).
-static bool gauss_rule(int G, GaussRule &r)
-{
-    double x[5] = {0, 0, 0, 0, 0}, w[5] = {0, 0, 0, 0, 0};
-    switch (G) {
-    case 1: x[0] = 0.0; w[0] = 2.0; break;
-    case 2: x[0] = -1.0 / std::sqrt(3.0); x[1] = -x[0]; w[0] = w[1] = 1.0; break;
-    case 3:
-        x[0] = -std::sqrt(3.0 / 5.0); x[1] = 0.0; x[2] = -x[0];
-        w[0] = w[2] = 5.0 / 9.0; w[1] = 8.0 / 9.0;
-        break;
-    case 4: {
-        const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
-        const double b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
-        x[0] = -b; x[1] = -a; x[2] = a; x[3] = b;
-        w[0] = w[3] = (18.0 - std::sqrt(30.0)) / 36.0;
-        w[1] = w[2] = (18.0 + std::sqrt(30.0)) / 36.0;
-        break;
-    }
-    case 5: {
-        const double a = std::sqrt(5.0 - 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
-        const double b = std::sqrt(5.0 + 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
-        x[0] = -b; x[1] = -a; x[2] = 0.0; x[3] = a; x[4] = b;
-        w[0] = w[4] = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
-        w[1] = w[3] = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
-        w[2] = 128.0 / 225.0;
-        break;
-    }
-    default: return false;
-    }
-    for (int k = 0; k < kMaxGauss; ++k) {
-        r.s[k] = (k < G) ? 0.5 * (1.0 + x[k]) : 0.0;
-        r.w[k] = (k < G) ? 0.5 * w[k] : 0.0;
-    }
-    return true;
-}
 
 static bool valid_bc(int b) { return b >= DSVE_BC_TRANSMISSIVE && b <= DSVE_BC_DIRICHLET; }
 
@@ -227,7 +191,6 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     c->arch = prop.gcnArchName;
     c->stream = (hipStream_t)stream;
     HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    gauss_rule(c->G, c->rule);
 
     const int64_t C = c->n_channels;
     c->h_eoff.resize(C + 1);
@@ -243,9 +206,13 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     HIP_TRY(c, hipMalloc(&c->pp_q, sizeof(double) * c->n_cells));
     HIP_TRY(c, hipMalloc(&c->pp_z, sizeof(double) * c->n_cells));
     HIP_TRY(c, hipMalloc(&c->pp_t, sizeof(double) * C));
-    HIP_TRY(c, hipMalloc(&c->d_amax, sizeof(unsigned long long) * 3 * C));
+    if (amax_split_of_kernels() != kAmaxSplitMax)
+        return fail(c, DSVE_E_HIP, "kernels built with another CFL sub-slot count than the host code");
+    c->amax_cs = amax_stride(C);
+    c->amax_slot = (int64_t)kAmaxSplitMax * c->amax_cs;
+    HIP_TRY(c, hipMalloc(&c->d_amax, sizeof(unsigned long long) * 3 * c->amax_slot));
     HIP_TRY(c, hipMalloc(&c->d_flags, sizeof(unsigned int) * 4));
-    HIP_TRY(c, launch_fill_u64(c->d_amax, 3 * C, 0ull, c->stream));
+    HIP_TRY(c, launch_fill_u64(c->d_amax, 3 * c->amax_slot, 0ull, c->stream));
     HIP_TRY(c, launch_fill_u32(c->d_flags, 4, 0u, c->stream));
     dsve_status st = build_tile_table(c, c->tile);
     if (st != DSVE_OK) return st;
@@ -464,7 +431,7 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
     FluctArgs a{};
     a.hL = hL; a.qL = qL; a.zL = zL; a.hR = hR; a.qR = qR; a.zR = zR;
     a.Dm = Dm; a.Dp = Dp; a.flags = ctx->d_flags; a.n = n;
-    a.g = ctx->g; a.ci = ctx->h_ch[0]; a.rule = ctx->rule;
+    a.g = ctx->g; a.ci = ctx->h_ch[0];
     HIP_TRY(ctx, launch_fluct(a, ctx->precision, ctx->G, ctx->cl, ctx->stream));
     return DSVE_OK;
 }
@@ -505,10 +472,32 @@ dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const do
     dsve_status st = enqueue_cfl(ctx, h, q, z, am);
     if (st != DSVE_OK) return st;
     HIP_TRY(ctx, launch_dt(am, ctx->d_ch, 1, dt_dev, ctx->stream));
+    HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, ctx->amax_slot, 0ull, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_amax, am, sizeof(unsigned long long), hipMemcpyDeviceToDevice,
                                 ctx->stream));
     ctx->last_amax_slot = 0;
     return DSVE_OK;
+}
+
+// Persistent grid: blocks_per_cu workgroups per compute unit (0 = as many as fit at once),
+// never more than there are tiles.
+static int grid_of(const dsve_ctx *ctx)
+{
+    const int bpc = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
+                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->cl, ctx->tile);
+    return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)bpc * ctx->cus);
+}
+
+// CFL sub-slots in use.  Automatic choice: spread the per-workgroup merges over 4 sub-slots
+// when many workgroups share a channel and each merges after a few tiles (the merges of one
+// step then come close together on one address); one sub-slot otherwise, which keeps the
+// per-tile read of the maximum to one load.
+static int split_of(const dsve_ctx *ctx, int grid)
+{
+    if (ctx->cfl_split > 0) return ctx->cfl_split;
+    const double wg_per_channel = (double)grid / (double)ctx->n_channels;
+    const double tiles_per_wg = (double)ctx->n_tiles / (double)grid;
+    return (wg_per_channel >= 256.0 && tiles_per_wg <= 4.0) ? 4 : 1;
 }
 
 // Arguments of step j (phase j mod 6) of a run starting from the caller's buffers.
@@ -526,9 +515,11 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
     a.ch = ctx->d_ch;
     a.eoff = ctx->d_eoff;
     a.tile_chan = ctx->d_tile_chan;
-    a.amax_cur = ctx->d_amax + (j % 3) * C;
-    a.amax_next = ctx->d_amax + ((j + 1) % 3) * C;
-    a.amax_clear = ctx->d_amax + ((j + 2) % 3) * C;
+    a.amax_cur = ctx->d_amax + (j % 3) * ctx->amax_slot;
+    a.amax_next = ctx->d_amax + ((j + 1) % 3) * ctx->amax_slot;
+    a.amax_clear = ctx->d_amax + ((j + 2) % 3) * ctx->amax_slot;
+    a.amax_stride = ctx->amax_cs;
+    a.amax_split = split_of(ctx, grid_of(ctx));
     a.t_cur = even ? t : ctx->pp_t;
     a.t_next = even ? ctx->pp_t : t;
     a.flags = ctx->d_flags;
@@ -536,25 +527,16 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
     a.n_tiles = ctx->n_tiles;
     a.n_channels = (int32_t)C;
     a.g = ctx->g;
-    a.rule = ctx->rule;
     return a;
-}
-
-// Persistent grid: blocks_per_cu workgroups per compute unit (0 = as many as fit at once),
-// never more than there are tiles.
-static int grid_of(const dsve_ctx *ctx)
-{
-    const int bpc = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
-                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->cl, ctx->tile);
-    return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)bpc * ctx->cus);
 }
 
 static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, double *t)
 {
     const int grid = grid_of(ctx);
     const void *key[4] = {h, q, z, t};
+    const int split = split_of(ctx, grid);
     if (ctx->gexec && ctx->g_steps == ctx->graph_steps && ctx->g_tile == ctx->tile &&
-        ctx->g_grid == grid && std::equal(key, key + 4, ctx->g_key))
+        ctx->g_grid == grid && ctx->g_split == split && std::equal(key, key + 4, ctx->g_key))
         return DSVE_OK;
     free_graph(ctx);
     hipGraph_t graph = nullptr;
@@ -578,6 +560,7 @@ static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, 
     ctx->g_steps = ctx->graph_steps;
     ctx->g_tile = ctx->tile;
     ctx->g_grid = grid;
+    ctx->g_split = split;
     std::copy(key, key + 4, ctx->g_key);
     return DSVE_OK;
 }
@@ -588,11 +571,10 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
     if (!h || !q || !z || !t) return fail(ctx, DSVE_E_ARG, "null pointer");
     if (n_steps < 0) return fail(ctx, DSVE_E_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return DSVE_OK;
-    const int64_t C = ctx->n_channels;
     dsve_status st = build_tile_table(ctx, ctx->tile);
     if (st != DSVE_OK) return st;
-    // slots: clear all three, CFL max of W^0 into slot 0
-    HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, 3 * C, 0ull, ctx->stream));
+    // slots: clear all three, CFL max of W^0 into sub-slot 0 of slot 0
+    HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, 3 * ctx->amax_slot, 0ull, ctx->stream));
     st = enqueue_cfl(ctx, h, q, z, ctx->d_amax);
     if (st != DSVE_OK) return st;
     int done = 0;
@@ -645,12 +627,14 @@ dsve_status dsve_sync(dsve_ctx *ctx)
     if (flags[0]) return fail(ctx, DSVE_E_NONHYPERBOLIC, "complex eigenvalues (arccos argument out of range)");
     if (ctx->last_amax_slot >= 0) {
         const int64_t C = ctx->n_channels;
-        std::vector<unsigned long long> am(C);
-        HIP_TRY(ctx, hipMemcpy(am.data(), ctx->d_amax + ctx->last_amax_slot * C, sizeof(unsigned long long) * C,
-                               hipMemcpyDeviceToHost));
+        std::vector<unsigned long long> am(ctx->amax_slot);
+        HIP_TRY(ctx, hipMemcpy(am.data(), ctx->d_amax + ctx->last_amax_slot * ctx->amax_slot,
+                               sizeof(unsigned long long) * ctx->amax_slot, hipMemcpyDeviceToHost));
         for (int64_t k = 0; k < C; ++k) {
+            unsigned long long m = am[k];
+            for (int s = 1; s < kAmaxSplitMax; ++s) m = std::max(m, am[s * ctx->amax_cs + k]);
             double v;
-            std::memcpy(&v, &am[k], sizeof v);
+            std::memcpy(&v, &m, sizeof v);
             if (!std::isfinite(v) || !(v > 0.0)) {
                 char buf[128];
                 std::snprintf(buf, sizeof buf, "non-finite or zero CFL speed in channel %lld", (long long)k);
@@ -690,6 +674,23 @@ dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, 
     return DSVE_OK;
 }
 
+dsve_status dsve_set_cfl_split(dsve_ctx *ctx, int split)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (split != 0 && split != 1 && split != 2 && split != 4)
+        return fail(ctx, DSVE_E_ARG, "cfl_split must be 0, 1, 2 or 4");
+    if (split != ctx->cfl_split) free_graph(ctx);
+    ctx->cfl_split = split;
+    return DSVE_OK;
+}
+
+dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split)
+{
+    if (!ctx || !split) return DSVE_E_ARG;
+    *split = split_of(ctx, grid_of(ctx));
+    return DSVE_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -712,7 +713,7 @@ static std::string tune_key(const dsve_ctx *ctx)
     return os.str();
 }
 
-static bool cache_lookup(const char *path, const std::string &key, int &tile, int &bpc)
+static bool cache_lookup(const char *path, const std::string &key, int &tile, int &bpc, int &split)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -727,12 +728,15 @@ static bool cache_lookup(const char *path, const std::string &key, int &tile, in
         if (pt == std::string::npos || pb == std::string::npos) continue;
         tile = std::atoi(line.c_str() + pt + 8);
         bpc = std::atoi(line.c_str() + pb + 17);
+        const size_t ps = line.find("\"cfl_split\": ");
+        split = ps == std::string::npos ? 0 : std::atoi(line.c_str() + ps + 13);
         return true;
     }
     return false;
 }
 
-static void cache_store(const char *path, const std::string &key, int tile, int bpc, double ms)
+static void cache_store(const char *path, const std::string &key, int tile, int bpc, int split,
+                        double ms)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -746,7 +750,7 @@ static void cache_store(const char *path, const std::string &key, int tile, int 
     std::ofstream o(path, std::ios::trunc);
     for (auto &l : keep) o << l << "\n";
     o << "{\"key\": \"" << key << "\", \"tile\": " << tile << ", \"blocks_per_cu\": " << bpc
-      << ", \"ms_per_step\": " << ms << "}\n";
+      << ", \"cfl_split\": " << split << ", \"ms_per_step\": " << ms << "}\n";
 }
 
 extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q,
@@ -757,9 +761,11 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     if (!h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
     if (trial_steps < 2 || trial_steps > 1000) return fail(ctx, DSVE_E_ARG, "trial_steps must be in [2, 1000]");
     const std::string key = tune_key(ctx);
-    int tile = 0, bpc = 0;
-    if (cache_lookup(cache_path, key, tile, bpc))
-        return dsve_set_launch(ctx, tile, bpc, ctx->graph_steps);
+    int tile = 0, bpc = 0, split = 0;
+    if (cache_lookup(cache_path, key, tile, bpc, split)) {
+        dsve_status st = dsve_set_launch(ctx, tile, bpc, ctx->graph_steps);
+        return st != DSVE_OK ? st : dsve_set_cfl_split(ctx, split);
+    }
 
     const size_t bytes = sizeof(double) * ctx->n_cells;
     double *sh = nullptr, *sq = nullptr, *sz = nullptr, *st_ = nullptr;
@@ -781,36 +787,53 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     // graphs (a warm-up run captures it, the timed run replays it; 12-step graphs keep the
     // trials short), direct launches if not.
     const int save_graph = ctx->graph_steps;
+    const int save_split = ctx->cfl_split;
     const int tg = save_graph > 0 ? std::min(save_graph, 12) : 0;
     const int warm = tg > 0 ? tg : 2;
     const int timed = tg > 0 ? std::max(tg, (trial_steps + tg - 1) / tg * tg) : trial_steps;
-    float best = 1e30f;
-    int best_tile = ctx->tile, best_bpc = ctx->blocks_per_cu;
     dsve_status status = DSVE_OK;
+    auto trial = [&](int ti, int bi, int sp, float &ms) -> dsve_status {
+        dsve_status s = dsve_set_launch(ctx, ti, bi, tg);
+        if (s == DSVE_OK) s = dsve_set_cfl_split(ctx, sp);
+        if (s != DSVE_OK) return s;
+        (void)hipMemcpyAsync(sh, h, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+        (void)hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+        (void)hipMemcpyAsync(sz, z, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+        (void)launch_fill_u64(reinterpret_cast<unsigned long long *>(st_), ctx->n_channels, 0ull, ctx->stream);
+        s = run_steps(ctx, sh, sq, sz, warm, st_);   // warm-up (and capture)
+        if (s != DSVE_OK) return s;
+        (void)hipEventRecord(e0, ctx->stream);
+        s = run_steps(ctx, sh, sq, sz, timed, st_);
+        if (s != DSVE_OK) return s;
+        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return DSVE_OK;
+    };
+    // (time, tile, blocks per CU, sub-slots); first pass with the automatic sub-slot count
+    struct Cand { float ms; int tile, bpc, split; };
+    std::vector<Cand> cands;
     for (int ti : tiles) {
         for (int bi : bpcs) {
-            status = dsve_set_launch(ctx, ti, bi, tg);
-            if (status != DSVE_OK) break;
-            (void)hipMemcpyAsync(sh, h, bytes, hipMemcpyDeviceToDevice, ctx->stream);
-            (void)hipMemcpyAsync(sq, q, bytes, hipMemcpyDeviceToDevice, ctx->stream);
-            (void)hipMemcpyAsync(sz, z, bytes, hipMemcpyDeviceToDevice, ctx->stream);
-            (void)launch_fill_u64(reinterpret_cast<unsigned long long *>(st_), ctx->n_channels, 0ull, ctx->stream);
-            status = run_steps(ctx, sh, sq, sz, warm, st_);   // warm-up (and capture)
-            if (status != DSVE_OK) break;
-            (void)hipEventRecord(e0, ctx->stream);
-            status = run_steps(ctx, sh, sq, sz, timed, st_);
-            if (status != DSVE_OK) break;
-            (void)hipEventRecord(e1, ctx->stream);
-            (void)hipEventSynchronize(e1);
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
-                best_tile = ti;
-                best_bpc = bi;
-            }
+            status = trial(ti, bi, 0, ms);
+            if (status != DSVE_OK) break;
+            cands.push_back({ms, ti, bi, 0});
         }
         if (status != DSVE_OK) break;
+    }
+    // second pass: the three fastest launches with each sub-slot count set explicitly
+    if (status == DSVE_OK) {
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        const size_t top = std::min<size_t>(3, cands.size());
+        for (size_t k = 0; k < top && status == DSVE_OK; ++k) {
+            for (int sp : {1, 4}) {
+                float ms = 0.f;
+                status = trial(cands[k].tile, cands[k].bpc, sp, ms);
+                if (status != DSVE_OK) break;
+                cands.push_back({ms, cands[k].tile, cands[k].bpc, sp});
+            }
+        }
     }
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipEventDestroy(e0);
@@ -820,8 +843,12 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     (void)hipFree(sz);
     (void)hipFree(st_);
     if (status != DSVE_OK) return status;
-    dsve_status st = dsve_set_launch(ctx, best_tile, best_bpc, save_graph);
+    Cand best{1e30f, ctx->tile, ctx->blocks_per_cu, save_split};
+    for (const Cand &c : cands)
+        if (c.ms < best.ms) best = c;
+    dsve_status st = dsve_set_launch(ctx, best.tile, best.bpc, save_graph);
+    if (st == DSVE_OK) st = dsve_set_cfl_split(ctx, best.split);
     if (st != DSVE_OK) return st;
-    cache_store(cache_path, key, best_tile, best_bpc, best / timed);
+    cache_store(cache_path, key, best.tile, best.bpc, best.split, best.ms / timed);
     return DSVE_OK;
 }

@@ -269,14 +269,13 @@ __device__ __forceinline__ double speed_dot(double h, double q, double g, const 
 // DOT fluctuations of one edge with the numerical eigen-decomposition at every node.
 template <int G, int CL>
 __device__ __forceinline__ void fluct_dot(double hL, double qL, double zL, double hR, double qR,
-                                          double zR, double g, const Closure &K,
-                                          const GaussRule &rule, double Dm[3], double Dp[3],
-                                          bool &bad)
+                                          double zR, double g, const Closure &K, double Dm[3],
+                                          double Dp[3], bool &bad)
 {
     const double dW[3] = {hR - hL, qR - qL, zR - zL};
     double SA[3] = {0.0, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < G; ++k) {
-        const double s = rule.s[k], w = rule.w[k];
+        const double s = Gauss<G>::s[k], w = Gauss<G>::w[k];
         double A[3][3], lam[3], R[3][3], Ri[3][3];
         flux_matrix<CL>(fma(s, dW[0], hL), fma(s, dW[1], qL), g, K, A);
         bad |= !eig3_numeric(A, lam, R);

@@ -8,8 +8,13 @@
 //   eoff       int64 [C+1]: first edge of each channel in the flat edge space;
 //              channel c has N_c + 1 edges, eoff[c] = off[c] + c, eoff[C] = total edges
 //   tile_chan  int32 per tile: channel of the tile's first edge
-//   amax       uint64 [3][C]: bit patterns of the per-channel CFL maximum, rotated
-//              through three slots (read n%3, atomic-max (n+1)%3, clear (n+2)%3)
+//   amax       uint64 [3][4][Cs]: bit patterns of the per-channel CFL maximum, rotated
+//              through three slots (read n%3, atomic-max (n+1)%3, clear (n+2)%3); each slot
+//              holds up to 4 sub-slots per channel, Cs = C rounded up to 512 entries (4 KiB)
+//              apart, and the channel's maximum is the maximum over its sub-slots.  With S
+//              sub-slots in use a workgroup merges its partial maximum into sub-slot
+//              (workgroup index mod S), so the atomics of one step spread over S addresses
+//              instead of queueing on one (S = 1, 2 or 4, a launch parameter).
 //   clocks     float64 [C] twice (the caller's array and the context's copy): step n reads one
 //              and writes t + dt to the other, so every thread sees the step's start time
 //   flags      uint32 [4]: [0] non-hyperbolic state seen
@@ -85,10 +90,42 @@ struct alignas(16) ChanInfo {
 };
 static_assert(sizeof(ChanInfo) == 160, "ChanInfo layout changed");
 
-struct GaussRule {
-    double s[kMaxGauss];
-    double w[kMaxGauss];
+// Gauss-Legendre rules on [0, 1] for G = 1..5 points (Sec. 3.1: the path integral of the
+// fluctuations): nodes s = (1 + x)/2 of the Legendre roots x, from their closed forms, and
+// weights halved so they sum to one, to 21 significant digits.  Compile-time constants of the
+// kernels, which are instantiated per G.
+template <int G> struct Gauss;
+template <> struct Gauss<1> {
+    static constexpr double s[1] = {5.000000000000000000000e-1};
+    static constexpr double w[1] = {1.000000000000000000000e+0};
 };
+template <> struct Gauss<2> {
+    static constexpr double s[2] = {2.113248654051871177454e-1, 7.886751345948128822546e-1};
+    static constexpr double w[2] = {5.000000000000000000000e-1, 5.000000000000000000000e-1};
+};
+template <> struct Gauss<3> {
+    static constexpr double s[3] = {1.127016653792583114821e-1, 5.000000000000000000000e-1,
+                                    8.872983346207416885179e-1};
+    static constexpr double w[3] = {2.777777777777777777778e-1, 4.444444444444444444444e-1,
+                                    2.777777777777777777778e-1};
+};
+template <> struct Gauss<4> {
+    static constexpr double s[4] = {6.943184420297371238803e-2, 3.300094782075718675987e-1,
+                                    6.699905217924281324013e-1, 9.305681557970262876120e-1};
+    static constexpr double w[4] = {1.739274225687269286865e-1, 3.260725774312730713135e-1,
+                                    3.260725774312730713135e-1, 1.739274225687269286865e-1};
+};
+template <> struct Gauss<5> {
+    static constexpr double s[5] = {4.691007703066800360119e-2, 2.307653449471584544818e-1,
+                                    5.000000000000000000000e-1, 7.692346550528415455182e-1,
+                                    9.530899229693319963988e-1};
+    static constexpr double w[5] = {1.184634425280945437571e-1, 2.393143352496832340206e-1,
+                                    2.844444444444444444444e-1, 2.393143352496832340206e-1,
+                                    1.184634425280945437571e-1};
+};
+
+constexpr int kAmaxSplitMax = 4;   // CFL sub-slots per channel allocated in each slot
+inline int64_t amax_stride(int64_t n_channels) { return (n_channels + 511) / 512 * 512; }
 
 struct StepArgs {
     const double *h, *q, *z;     // W^n
@@ -96,9 +133,11 @@ struct StepArgs {
     const ChanInfo *ch;
     const int64_t *eoff;         // [C+1]
     const int32_t *tile_chan;    // [n_tiles]
-    const unsigned long long *amax_cur;  // [C] CFL max of W^n
-    unsigned long long *amax_next;       // [C] CFL max of W^{n+1} (pre-cleared)
-    unsigned long long *amax_clear;      // [C] slot to clear for step n+1
+    const unsigned long long *amax_cur;  // [S][Cs] CFL max of W^n
+    unsigned long long *amax_next;       // [S][Cs] CFL max of W^{n+1} (pre-cleared)
+    unsigned long long *amax_clear;      // [S][Cs] slot to clear for step n+1
+    int64_t amax_stride;                 // Cs
+    int32_t amax_split;                  // S: sub-slots in use (1, 2 or 4)
     const double *t_cur;         // [C] clocks at the start of the step
     double *t_next;              // [C] clocks after it
     unsigned int *flags;
@@ -106,7 +145,6 @@ struct StepArgs {
     int64_t n_tiles;
     int32_t n_channels;
     double g;
-    GaussRule rule;
 };
 
 struct CflArgs {
@@ -127,7 +165,6 @@ struct FluctArgs {
     int64_t n;
     double g;
     ChanInfo ci;   // closure constants of the context (channel 0)
-    GaussRule rule;
 };
 
 // Host-side launchers (dsve_kernels.hip).  All enqueue on `stream` and return the
@@ -148,5 +185,7 @@ hipError_t launch_dt(const unsigned long long *amax, const ChanInfo *ch, int32_t
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream_t stream);
+// kAmaxSplitMax as compiled into the kernels (the host code checks it against its own).
+int amax_split_of_kernels();
 
 }  // namespace dsve

@@ -88,6 +88,20 @@ __device__ __forceinline__ void flush_max(unsigned long long *slot, unsigned lon
     if (v > cur) atomicMax(slot, v);
 }
 
+// CFL maximum of channel c: the largest of its S sub-slots, as a double.  The floating-point
+// maximum drops a NaN sub-slot when another holds a number; a NaN state still shows, since its
+// cells stay NaN and the host's check of the last slot orders bit patterns as unsigned
+// integers, where NaN is the largest.
+__device__ __forceinline__ double amax_of(const unsigned long long *__restrict__ AM, int c,
+                                         int64_t stride, int split)
+{
+    double m = __longlong_as_double((long long)AM[c]);
+#pragma unroll
+    for (int s = 1; s < kAmaxSplitMax; ++s)
+        if (s < split) m = fmax(m, __longlong_as_double((long long)AM[c + s * stride]));
+    return m;
+}
+
 __device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
 {
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1u);
@@ -96,13 +110,12 @@ __device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
 // Edge fluctuation and cell speed for the chosen precision and closure form.
 template <int G, int PREC, int CL>
 __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, double hR, double qR,
-                                           double zR, double g, const Closure &K,
-                                           const GaussRule &rule, double Dm[3], double Dp[3],
-                                           bool &bad)
+                                           double zR, double g, const Closure &K, double Dm[3],
+                                           double Dp[3], bool &bad)
 {
-    if constexpr (PREC == PREC_FP64) fluct64<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
-    else if constexpr (PREC == PREC_MIXED) fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
-    else fluct_dot<G, CL>(hL, qL, zL, hR, qR, zR, g, K, rule, Dm, Dp, bad);
+    if constexpr (PREC == PREC_FP64) fluct64<G, CL>(hL, qL, zL, hR, qR, zR, g, K, Dm, Dp, bad);
+    else if constexpr (PREC == PREC_MIXED) fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, Dm, Dp, bad);
+    else fluct_dot<G, CL>(hL, qL, zL, hR, qR, zR, g, K, Dm, Dp, bad);
 }
 
 template <int PREC, int CL>
@@ -155,13 +168,16 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
     int nx2_home = k + stride < A.n_tiles ? TC[k + stride] : 0;
     int64_t nx_eo0 = EO[nx_home], nx_eo1 = EO[nx_home + 1];
     int nx_bcl = CH[nx_home].bcl, nx_bcr = CH[nx_home].bcr;
-    unsigned long long nx_am = AM[nx_home];
+    double nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
+    // this workgroup's sub-slot of the CFL maxima it merges into (S is a power of two)
+    unsigned long long *const amax_mine =
+        A.amax_next + (int64_t)(blockIdx.x & (unsigned)(A.amax_split - 1)) * A.amax_stride;
     for (; k < A.n_tiles; k += stride) {
         const int home = nx_home;
         const int64_t eo0 = nx_eo0, eo1 = nx_eo1;
         const int64_t h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
         const int h_bcl = nx_bcl, h_bcr = nx_bcr;
-        const unsigned long long am_home = nx_am;
+        const double am_home = nx_am;
         if (t == 0) s_acc = 0ull;
         const int64_t ge = k * (int64_t)(T - 1) + t;
         const bool have_edge = ge < A.n_edges;
@@ -209,7 +225,8 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             nx_eo1 = EO[nx_home + 1];
             nx_bcl = CH[nx_home].bcl;
             nx_bcr = CH[nx_home].bcr;
-            nx_am = AM[nx_home];
+            // the CFL maximum of W^n is fixed during the step: reuse it within a channel
+            if (nx_home != home) nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (have_edge) {
@@ -223,7 +240,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
                 qRe = ghost_q(ci.bcr, ci.br, qR);
                 if (ci.bcr == BC_DIRICHLET) zRe = ghost_z(ci.bcr, ci.br, zR, A.t_cur[c]);
             }
-            edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zRe, A.g, K, A.rule, Dm, Dp, bad);
+            edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zRe, A.g, K, Dm, Dp, bad);
         }
         s_dm[t] = Dm[0];
         s_dm[T + t] = Dm[1];
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const bool upd = have_edge && (t < T - 1) && (e < ncell);
         unsigned long long sp_bits = 0ull;
         if (upd) {
-            const double amax = __longlong_as_double((long long)(c == home ? am_home : AM[c]));
+            const double amax = c == home ? am_home : amax_of(AM, c, A.amax_stride, A.amax_split);
             const double dt = ci.cfl_dx * rcp_h(amax);
             const double r = dt * ci.inv_dx;
             const int64_t i = cell0 + e;
@@ -250,14 +267,17 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             if (e == 0) {
                 A.t_next[c] = A.t_cur[c] + dt;
                 A.amax_clear[c] = 0ull;
+#pragma unroll
+                for (int s = 1; s < kAmaxSplitMax; ++s)
+                    if (s < A.amax_split) A.amax_clear[c + s * A.amax_stride] = 0ull;
             }
         }
         raise_flag(A.flags, bad);
-        reduce_channel_max(sp_bits, c, upd, home, &s_acc, A.amax_next);
+        reduce_channel_max(sp_bits, c, upd, home, &s_acc, amax_mine);
         __syncthreads();
         if (t == 0) {
             if (home != reg_chan) {
-                if (reg_chan >= 0) flush_max(&A.amax_next[reg_chan], reg_acc);
+                if (reg_chan >= 0) flush_max(&amax_mine[reg_chan], reg_acc);
                 reg_chan = home;
                 reg_acc = s_acc;
             } else {
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             }
         }
     }
-    if (t == 0 && reg_chan >= 0) flush_max(&A.amax_next[reg_chan], reg_acc);
+    if (t == 0 && reg_chan >= 0) flush_max(&amax_mine[reg_chan], reg_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,8 +347,8 @@ __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
     bool bad = false;
     if (e < A.n) {
         double Dm[3], Dp[3];
-        edge_fluct<G, PREC, CL>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci), A.rule,
-                            Dm, Dp, bad);
+        edge_fluct<G, PREC, CL>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci),
+                                Dm, Dp, bad);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             A.Dm[r * A.n + e] = Dm[r];
@@ -514,5 +534,7 @@ hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
+
+int amax_split_of_kernels() { return kAmaxSplitMax; }
 
 }  // namespace dsve

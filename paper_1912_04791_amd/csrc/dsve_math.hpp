@@ -325,17 +325,17 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
 // DOT fluctuations of one edge, FP64 throughout.
 template <int G, int CL>
 __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double hR, double qR,
-                                        double zR, double g, const Closure &K, const GaussRule &rule,
-                                        double Dm[3], double Dp[3], bool &bad)
+                                        double zR, double g, const Closure &K, double Dm[3],
+                                        double Dp[3], bool &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     double SA[3] = {0.0, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
-        const double s = rule.s[k];
+        const double s = Gauss<G>::s[k];
         Eig64 E;
         eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E, bad);
-        node_accumulate64(E, rule.w[k], dh, dq, dz, SA, SB);
+        node_accumulate64(E, Gauss<G>::w[k], dh, dq, dz, SA, SB);
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -418,9 +418,8 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
 
 template <int G, int CL>
 __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, double hR, double qR,
-                                            double zR, double g, const Closure &K,
-                                            const GaussRule &rule, double Dm[3], double Dp[3],
-                                            bool &bad)
+                                            double zR, double g, const Closure &K, double Dm[3],
+                                            double Dp[3], bool &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     const float dhf = (float)dh, dqf = (float)dq, dzf = (float)dz;
@@ -430,15 +429,15 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     double SA64[3] = {0.0, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
-        const float sf = (float)rule.s[k];
+        const float sf = (float)Gauss<G>::s[k];
         EigF E;
         if (eigf<CL>(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, K, E)) {
-            node_accumulatef(E, (float)rule.w[k], dhf, dqf, dzf, SA, SB);
+            node_accumulatef(E, (float)Gauss<G>::w[k], dhf, dqf, dzf, SA, SB);
         } else {
-            const double s = rule.s[k];
+            const double s = Gauss<G>::s[k];
             Eig64 E64;
             eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, bad);
-            node_accumulate64(E64, rule.w[k], dh, dq, dz, SA64, SB64);
+            node_accumulate64(E64, Gauss<G>::w[k], dh, dq, dz, SA64, SB64);
         }
     }
 #pragma unroll

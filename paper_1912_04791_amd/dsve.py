@@ -110,14 +110,17 @@ lib.dsve_set_launch.argtypes = [_ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 lib.dsve_get_launch.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]
 lib.dsve_autotune.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_char_p]
+lib.dsve_set_cfl_split.argtypes = [_ctxp, ctypes.c_int]
+lib.dsve_get_cfl_split.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int)]
 lib.dsve_device_cus.argtypes = [_ctxp]
 lib.dsve_device_cus.restype = ctypes.c_int
-assert lib.dsve_abi_version() == 2, "libdsve ABI version mismatch"
+assert lib.dsve_abi_version() == 3, "libdsve ABI version mismatch"
 
 ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destroy",
                 "dot_edge_fluct", "cell_update", "cfl_reduce", "adot_step", "adot_step_batched",
                 "dsve_sync", "dsve_last_error", "dsve_clear_error", "dsve_set_launch",
-                "dsve_get_launch", "dsve_autotune", "dsve_device_cus")
+                "dsve_get_launch", "dsve_set_cfl_split", "dsve_get_cfl_split", "dsve_autotune",
+                "dsve_device_cus")
 
 
 class DsveError(RuntimeError):
@@ -311,6 +314,15 @@ class Context:
         self._check(lib.dsve_get_launch(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                     "dsve_get_launch")
         return a.value, b.value, c.value
+
+    def set_cfl_split(self, split: int):
+        """CFL sub-slots per channel (1, 2 or 4; 0 = chosen from the launch shape)."""
+        self._check(lib.dsve_set_cfl_split(self._h, split), "dsve_set_cfl_split")
+
+    def get_cfl_split(self) -> int:
+        v = ctypes.c_int()
+        self._check(lib.dsve_get_cfl_split(self._h, ctypes.byref(v)), "dsve_get_cfl_split")
+        return v.value
 
     def autotune(self, h, q, z, trial_steps: int = 10, cache_path: str | None = None):
         cp = cache_path.encode() if cache_path else None

@@ -32,10 +32,13 @@ def dsve():
     return d
 
 
-def run_gpu(dsve, torch, wl, steps=None, precision="fp64", launch=None, autotune=False):
+def run_gpu(dsve, torch, wl, steps=None, precision="fp64", launch=None, autotune=False, split=None):
     ctx = dsve.Context.from_workload(wl, precision=precision)
     if launch is not None:
         ctx.set_launch(*launch)
+    if split is not None:
+        ctx.set_cfl_split(split)
+        assert ctx.get_cfl_split() == split
     h, q, z, t = dsve.upload(wl)
     if autotune:   # the launch the benchmark times: tuned on a scratch copy of the state
         ctx.autotune(h, q, z, trial_steps=20)
@@ -180,6 +183,37 @@ def test_launch_configuration_does_not_change_bits(torch_dev, dsve):
             assert np.array_equal(a, b)
 
 
+def test_cfl_sub_slots_do_not_change_bits(torch_dev, dsve):
+    # the per-channel CFL maximum merged into 1, 2 or 4 sub-slots, with one tile per
+    # workgroup and with persistent workgroups, single channel and batched
+    for wl in (inputs.make_c2(n_cells=150_000, steps=42),
+               inputs.make_c4(n_channels=9, len_lo=100, len_hi=20_000, steps=42)):
+        outs = []
+        for launch in [(256, 64, 6), (128, 2, 0)]:
+            for split in (1, 2, 4):
+                outs.append(run_gpu(dsve, torch_dev, wl, launch=launch, split=split))
+        for o in outs[1:]:
+            for a, b in zip(o, outs[0]):
+                assert np.array_equal(a, b)
+
+
+def test_automatic_cfl_sub_slots(torch_dev, dsve):
+    # many single-tile workgroups on one channel: 4 sub-slots; persistent workgroups, or
+    # few workgroups per channel: 1
+    ctx = dsve.Context.from_workload(inputs.make_c2(n_cells=1 << 20, steps=1))
+    ctx.set_launch(256, 32, 60)
+    assert ctx.get_cfl_split() == 4
+    ctx.set_launch(256, 1, 60)
+    assert ctx.get_cfl_split() == 1
+    ctx.set_cfl_split(2)
+    assert ctx.get_cfl_split() == 2
+    ctx.close()
+    ctx = dsve.Context.from_workload(inputs.make_c4(n_channels=64, len_lo=100, len_hi=400, steps=1))
+    ctx.set_launch(256, 32, 60)
+    assert ctx.get_cfl_split() == 1
+    ctx.close()
+
+
 def test_repeat_runs_are_bitwise_identical(torch_dev, dsve):
     wl = inputs.make_c2(n_cells=70_000, steps=66)
     a = run_gpu(dsve, torch_dev, wl)
@@ -255,5 +289,9 @@ def test_bad_launch_arguments(torch_dev, dsve):
     for bad in [(96, 0, 60), (512, 0, 60), (256, -1, 60), (256, 1025, 60), (256, 0, 7)]:
         with pytest.raises(dsve.DsveError):
             ctx.set_launch(*bad)
+        ctx.clear_error()
+    for bad in (-1, 3, 8):
+        with pytest.raises(dsve.DsveError):
+            ctx.set_cfl_split(bad)
         ctx.clear_error()
     ctx.close()

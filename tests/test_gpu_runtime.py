@@ -56,6 +56,7 @@ def test_autotune_keeps_results_and_writes_cache(torch_dev, dsve, tmp_path):
     lines = [json.loads(l) for l in open(cache).read().splitlines() if l.strip()]
     assert len(lines) == 1 and lines[0]["tile"] == launch[0]
     assert lines[0]["blocks_per_cu"] == launch[1]
+    assert lines[0]["cfl_split"] in (0, 1, 4)
     ctx.adot_step(h, q, z, wl.steps, t)
     ctx.sync()
     for a, b in zip(to_np(h, q, z, t), to_np(h0, q0, z0, t0)):
@@ -66,6 +67,7 @@ def test_autotune_keeps_results_and_writes_cache(torch_dev, dsve, tmp_path):
     ctx2.set_launch(64, 1, 12)
     ctx2.autotune(h, q, z, trial_steps=4, cache_path=cache)
     assert ctx2.get_launch()[:2] == launch[:2]
+    assert ctx2.get_cfl_split() == ctx.get_cfl_split()
     for c in (ref_ctx, ctx, ctx2):
         c.close()
 
