@@ -484,7 +484,8 @@ dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const do
 static int grid_of(const dsve_ctx *ctx)
 {
     const int bpc = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
-                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->cl, ctx->tile);
+                                           : step_blocks_per_cu(ctx->precision, ctx->G, ctx->cl, ctx->tile,
+                                                                ctx->n_edges);
     return (int)std::min<int64_t>(ctx->n_tiles, (int64_t)bpc * ctx->cus);
 }
 

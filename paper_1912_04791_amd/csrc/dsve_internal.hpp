@@ -172,7 +172,10 @@ struct FluctArgs {
 hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
                        hipStream_t stream);
 // Workgroups of the step kernel that fit on one compute unit at once (occupancy query).
-int step_blocks_per_cu(int precision, int G, int cl, int tile);
+int step_blocks_per_cu(int precision, int G, int cl, int tile, int64_t n_edges);
+// The step kernel indexes cells and edges in 32 bits below 2^29 edges (byte offsets into the
+// state arrays then fit in 32 bits), in 64 bits from there on.
+inline bool step_needs_wide_index(int64_t n_edges) { return n_edges >= (int64_t(1) << 29); }
 hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t stream);
 hipError_t launch_fluct(const FluctArgs &a, int precision, int G, int cl, hipStream_t stream);
 // Cell update of one channel from given fluctuations; ch is the channel's record on the device

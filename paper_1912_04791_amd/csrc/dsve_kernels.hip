@@ -27,27 +27,29 @@
 
 namespace dsve {
 
-// Maximum over the 64 lanes of a wave, in lane 63, read back to every lane.  DPP lane moves
-// on the two 32-bit halves: swaps within quads, half-row and row mirrors (each lane then holds
-// its row of 16), then the broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows 2
-// and 3.  Lanes whose DPP source is out of range keep their own value.
-template <int CTRL, int ROWS>
+// Maximum over the 64 lanes of a wave of non-negative values (64-bit patterns), in lane 63,
+// read back to every lane.  DPP lane moves on the two 32-bit halves: swaps within quads,
+// half-row and row mirrors (each lane then holds its row of 16), then the broadcasts of lane
+// 15 of each row into the next row and of lane 31 into the upper half.  A lane whose DPP
+// source lies outside the wave reads 0, the identity of the maximum, so every lane is written
+// and no copy of the old value is needed.
+template <int CTRL>
 __device__ __forceinline__ unsigned long long dpp_umax(unsigned long long v)
 {
     const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
-    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
-    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
     const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
     return (o > v) ? o : v;
 }
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
-    v = dpp_umax<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
-    v = dpp_umax<0x4E, 0xf>(v);    // quad_perm [2, 3, 0, 1]
-    v = dpp_umax<0x141, 0xf>(v);   // row_half_mirror
-    v = dpp_umax<0x140, 0xf>(v);   // row_mirror
-    v = dpp_umax<0x142, 0xa>(v);   // row_bcast:15
-    v = dpp_umax<0x143, 0xc>(v);   // row_bcast:31
+    v = dpp_umax<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_umax<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_umax<0x141>(v);   // row_half_mirror
+    v = dpp_umax<0x140>(v);   // row_mirror
+    v = dpp_umax<0x142>(v);   // row_bcast:15
+    v = dpp_umax<0x143>(v);   // row_bcast:31
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
     return ((unsigned long long)hi << 32) | lo;
@@ -142,8 +144,27 @@ __device__ __forceinline__ double ghost_z(int bc, const double *b, double z, dou
     return bc == BC_DIRICHLET ? fma(t, b[3], b[2]) : z;
 }
 
+// Index arithmetic of the step kernel: 32-bit when the context has fewer than 2^29 edges (then
+// every byte offset into a state array fits in 32 bits and a load is an SGPR base plus a 32-bit
+// VGPR offset), 64-bit otherwise.
+template <bool WIDE> struct StepIdx { using type = int32_t; };
+template <> struct StepIdx<true> { using type = int64_t; };
+
+template <bool WIDE, typename I>
+__device__ __forceinline__ double ldx(const double *__restrict__ p, I i)
+{
+    if constexpr (WIDE) return p[i];
+    else return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(p) + ((uint32_t)i << 3));
+}
+template <bool WIDE, typename I>
+__device__ __forceinline__ void stx(double *__restrict__ p, I i, double v)
+{
+    if constexpr (WIDE) p[i] = v;
+    else *reinterpret_cast<double *>(reinterpret_cast<char *>(p) + ((uint32_t)i << 3)) = v;
+}
+
 // ---------------------------------------------------------------------------
-template <int G, int PREC, int CL>
+template <int G, int PREC, int CL, bool WIDE>
 __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(StepArgs A, const ChanInfo *__restrict__ CH,
                                                                            const int64_t *__restrict__ EO,
                                                                            const int32_t *__restrict__ TC,
@@ -151,6 +172,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
 {
     extern __shared__ double s_dm[];          // [3][T]
     __shared__ unsigned long long s_acc;
+    using Idx = typename StepIdx<WIDE>::type;
     const int T = blockDim.x;
     const int t = threadIdx.x;
     unsigned long long reg_acc = 0ull;        // used by thread 0 only
@@ -166,7 +188,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
     // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
     int nx_home = k < A.n_tiles ? TC[k] : 0;
     int nx2_home = k + stride < A.n_tiles ? TC[k + stride] : 0;
-    int64_t nx_eo0 = EO[nx_home], nx_eo1 = EO[nx_home + 1];
+    Idx nx_eo0 = (Idx)EO[nx_home], nx_eo1 = (Idx)EO[nx_home + 1];
     int nx_bcl = CH[nx_home].bcl, nx_bcr = CH[nx_home].bcr;
     double nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
     // this workgroup's sub-slot of the CFL maxima it merges into (S is a power of two)
@@ -174,22 +196,22 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         A.amax_next + (int64_t)(blockIdx.x & (unsigned)(A.amax_split - 1)) * A.amax_stride;
     for (; k < A.n_tiles; k += stride) {
         const int home = nx_home;
-        const int64_t eo0 = nx_eo0, eo1 = nx_eo1;
-        const int64_t h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
+        const Idx eo0 = nx_eo0, eo1 = nx_eo1;
+        const Idx h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
         const int h_bcl = nx_bcl, h_bcr = nx_bcr;
         const double am_home = nx_am;
         if (t == 0) s_acc = 0ull;
-        const int64_t ge = k * (int64_t)(T - 1) + t;
-        const bool have_edge = ge < A.n_edges;
+        const Idx ge = (Idx)k * (Idx)(T - 1) + t;
+        const bool have_edge = ge < (Idx)A.n_edges;
         int c = home;
-        int64_t eoc = eo0, cell0 = h_cell0, ncell = h_ncell;
+        Idx eoc = eo0, cell0 = h_cell0, ncell = h_ncell;
         int bcl = h_bcl, bcr = h_bcr;
         if (have_edge && ge >= eo1) {
             c = home + 1;
-            while (ge >= EO[c + 1]) ++c;
-            eoc = EO[c];
+            while (ge >= (Idx)EO[c + 1]) ++c;
+            eoc = (Idx)EO[c];
             cell0 = eoc - c;
-            ncell = EO[c + 1] - eoc - 1;
+            ncell = (Idx)EO[c + 1] - eoc - 1;
             bcl = CH[c].bcl;
             bcr = CH[c].bcr;
         }
@@ -199,21 +221,21 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         ChanInfo ci = hci;
         if (c != home) ci = CH[c];
         const Closure K = closure_of(ci);
-        const int64_t e = ge - eoc;
+        const Idx e = ge - eoc;
         bool bad = false;
         double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
         double hR = 0.0, qR = 0.0, zR = 0.0;
         double hL = 0.0, qL = 0.0, zL = 0.0;
-        const int64_t N = ncell, base = cell0;
+        const Idx N = ncell, base = cell0;
         if (have_edge) {
-            const int64_t il = (e == 0) ? (bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
-            const int64_t ir = (e == N) ? (bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
-            hL = A.h[il];
-            qL = A.q[il];
-            zL = A.z[il];
-            hR = A.h[ir];
-            qR = A.q[ir];
-            zR = A.z[ir];
+            const Idx il = (e == 0) ? (bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
+            const Idx ir = (e == N) ? (bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
+            hL = ldx<WIDE>(A.h, il);
+            qL = ldx<WIDE>(A.q, il);
+            zL = ldx<WIDE>(A.z, il);
+            hR = ldx<WIDE>(A.h, ir);
+            qR = ldx<WIDE>(A.q, ir);
+            zR = ldx<WIDE>(A.z, ir);
         }
         // the next tile's lookups go out after this tile's state loads and before its
         // arithmetic, so waiting for the state does not wait for them
@@ -221,8 +243,8 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         if (k + stride < A.n_tiles) {
             nx_home = nx2_home;
             nx2_home = k + 2 * stride < A.n_tiles ? TC[k + 2 * stride] : 0;
-            nx_eo0 = EO[nx_home];
-            nx_eo1 = EO[nx_home + 1];
+            nx_eo0 = (Idx)EO[nx_home];
+            nx_eo1 = (Idx)EO[nx_home + 1];
             nx_bcl = CH[nx_home].bcl;
             nx_bcr = CH[nx_home].bcr;
             // the CFL maximum of W^n is fixed during the step: reuse it within a channel
@@ -252,16 +274,16 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             const double amax = c == home ? am_home : amax_of(AM, c, A.amax_stride, A.amax_split);
             const double dt = ci.cfl_dx * rcp_h(amax);
             const double r = dt * ci.inv_dx;
-            const int64_t i = cell0 + e;
+            const Idx i = cell0 + e;
             // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i^n)
             // (Sec. 3, Eq. scheme; S from the friction slope when K_s is given)
             const double hn = hR - r * (s_dm[t + 1] + Dp[0]);
             double qn = qR - r * (s_dm[T + t + 1] + Dp[1]);
             const double zn = zR - r * (s_dm[2 * T + t + 1] + Dp[2]);
             if (ci.fric > 0.0) qn = fma(dt, friction_source(hR, qR, A.g, ci.fric), qn);
-            A.hn[i] = hn;
-            A.qn[i] = qn;
-            A.zn[i] = zn;
+            stx<WIDE>(A.hn, i, hn);
+            stx<WIDE>(A.qn, i, qn);
+            stx<WIDE>(A.zn, i, zn);
             const double sp = fabs(cell_speed<PREC, CL>(hn, qn, A.g, K, bad));
             sp_bits = (unsigned long long)__double_as_longlong(sp);
             if (e == 0) {
@@ -434,45 +456,60 @@ static hipError_t launch_fluct_prec(const FluctArgs &a, int G, int cl, hipStream
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, bool WIDE>
 static hipError_t launch_step_prec(const StepArgs &a, int G, int cl, int tile, int grid, hipStream_t s)
 {
     const size_t lds = sizeof(double) * 3 * (size_t)tile;
-#define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC>), dim3(grid), dim3(tile), lds, s, a, \
+#define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC, WIDE>), dim3(grid), dim3(tile), lds, s, a, \
                                                    a.ch, a.eoff, a.tile_chan, a.amax_cur)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_STEP)
 #undef DSVE_LAUNCH_STEP
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, bool WIDE>
 static hipError_t occupancy_query(int G, int cl, int tile, int &n)
 {
     const size_t lds = sizeof(double) * 3 * (size_t)tile;
     hipError_t e = hipErrorInvalidValue;
-#define DSVE_OCC(GG, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<GG, PREC, CC>, tile, lds)
+#define DSVE_OCC(GG, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<GG, PREC, CC, WIDE>, tile, lds)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_OCC)
 #undef DSVE_OCC
     return e;
 }
 
-int step_blocks_per_cu(int precision, int G, int cl, int tile)
+template <bool WIDE>
+static hipError_t occupancy_of(int precision, int G, int cl, int tile, int &n)
+{
+    return precision == PREC_MIXED ? occupancy_query<PREC_MIXED, WIDE>(G, cl, tile, n)
+         : precision == PREC_DOT   ? occupancy_query<PREC_DOT, WIDE>(G, cl, tile, n)
+                                   : occupancy_query<PREC_FP64, WIDE>(G, cl, tile, n);
+}
+
+int step_blocks_per_cu(int precision, int G, int cl, int tile, int64_t n_edges)
 {
     int n = 0;
-    const hipError_t e = precision == PREC_MIXED ? occupancy_query<PREC_MIXED>(G, cl, tile, n)
-                         : precision == PREC_DOT ? occupancy_query<PREC_DOT>(G, cl, tile, n)
-                                                 : occupancy_query<PREC_FP64>(G, cl, tile, n);
+    const hipError_t e = step_needs_wide_index(n_edges) ? occupancy_of<true>(precision, G, cl, tile, n)
+                                                       : occupancy_of<false>(precision, G, cl, tile, n);
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <bool WIDE>
+static hipError_t launch_step_w(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
+                                hipStream_t stream)
+{
+    if (precision == PREC_FP64) return launch_step_prec<PREC_FP64, WIDE>(a, G, cl, tile, grid, stream);
+    if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED, WIDE>(a, G, cl, tile, grid, stream);
+    if (precision == PREC_DOT) return launch_step_prec<PREC_DOT, WIDE>(a, G, cl, tile, grid, stream);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile, int grid,
                        hipStream_t stream)
 {
     if (tile < 64 || tile > kMaxTile || (tile & 63) || grid < 1) return hipErrorInvalidValue;
-    if (precision == PREC_FP64) return launch_step_prec<PREC_FP64>(a, G, cl, tile, grid, stream);
-    if (precision == PREC_MIXED) return launch_step_prec<PREC_MIXED>(a, G, cl, tile, grid, stream);
-    if (precision == PREC_DOT) return launch_step_prec<PREC_DOT>(a, G, cl, tile, grid, stream);
-    return hipErrorNotSupported;
+    return step_needs_wide_index(a.n_edges) ? launch_step_w<true>(a, precision, G, cl, tile, grid, stream)
+                                            : launch_step_w<false>(a, precision, G, cl, tile, grid, stream);
 }
 
 hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t stream)
