@@ -325,7 +325,7 @@ static void set_common(dsve_ctx *c, const dsve_params *p)
     // kernel arithmetic: the precision, or the numerical eigensolver of the original DOT
     c->precision = p->solver == DSVE_SOLVER_DOT ? PREC_DOT : p->precision;
     c->law = p->law;
-    c->cl = p->law == DSVE_LAW_GRASS ? CL_GRASS : CL_LAW;
+    c->cl = p->law;   // one kernel variant per law (the Grass law in closed form)
     c->G = p->n_gauss;
     c->g = p->g;
     c->cfl = p->cfl;

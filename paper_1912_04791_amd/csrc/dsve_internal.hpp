@@ -31,9 +31,11 @@ enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_INFLOW_Q = 2, BC_FIXED_DEPTH = 3
 // numerical eigen-decomposition of the original DOT solver (the baseline of the closed form).
 enum { PREC_FP64 = 0, PREC_MIXED = 1, PREC_DOT = 2 };
 enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN = 4 };
-// Kernel variants by closure: the Grass law in closed non-dimensional form, or any law through
-// the per-state coefficient b = xi dq_s/dq.
-enum { CL_GRASS = 0, CL_LAW = 1 };
+// Kernel variants by closure, one per law: the Grass law in closed non-dimensional form
+// (CL_GRASS), and each other law through the per-state coefficient b = xi dq_s/dq.  A context
+// has one law, so its kernels are compiled for that law alone.
+enum { CL_GRASS = LAW_GRASS, CL_GRASS_THR = LAW_GRASS_THR, CL_POWER = LAW_POWER, CL_MPM = LAW_MPM,
+       CL_VANRIJN = LAW_VANRIJN, kNumClosures = 5 };
 
 constexpr int kMaxGauss = 5;
 constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most
@@ -44,7 +46,7 @@ constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step
 #ifndef DSVE_MINW_MIXED
 #define DSVE_MINW_MIXED 4
 #endif
-// The general-closure variants carry the laws' power and root evaluations: fewer waves, more
+// The other closures carry their laws' power and root evaluations: fewer waves, more
 // registers per lane.
 #ifndef DSVE_MINW_LAW_FP64
 #define DSVE_MINW_LAW_FP64 2

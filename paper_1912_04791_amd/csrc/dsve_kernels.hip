@@ -8,10 +8,11 @@
 // k_fluct     pairwise fluctuations (dot_edge_fluct entry point).
 // k_update    cell update from given fluctuations (cell_update entry point).
 //
-// Every kernel comes in two closure forms: CL_GRASS (the Grass law in closed form, the
-// workloads of Sec. 4) and CL_LAW (any closure through b = xi dq_s/dq per state), and in three
-// arithmetic forms: FP64 and mixed closed form (Sec. 3.3), and FP64 with the numerical
-// eigen-decomposition of the original DOT solver (Sec. 3.1), the baseline of the closed form.
+// Every kernel comes in one closure form per bed-load law: CL_GRASS (the Grass law in closed
+// form, the workloads of Sec. 4) and the other laws through b = xi dq_s/dq per state (Sec. 2,
+// Sec. 5), and in three arithmetic forms: FP64 and mixed closed form (Sec. 3.3), and FP64 with
+// the numerical eigen-decomposition of the original DOT solver (Sec. 3.1), the baseline of the
+// closed form.
 //
 // Tiling of the step kernel: a workgroup of T threads takes T consecutive edges of the flat
 // edge space and updates the T-1 cells whose two faces both lie in the tile; tile k starts at
@@ -430,19 +431,45 @@ static inline unsigned int cfl_grid(int64_t n_cells)
     return full < 2048u ? full : 2048u;
 }
 
-// Dispatch over the compile-time variants: G in [1, 5] quadrature points, closure form.
+// Dispatch over the compile-time variants: G in [1, 5] quadrature points, closure (law).
 #define DSVE_DISPATCH_G_CL(G, CL, MACRO)                                                  \
-    switch ((G) * 2 + (CL)) {                                                             \
-    case 2: MACRO(1, CL_GRASS); break;                                                    \
-    case 3: MACRO(1, CL_LAW); break;                                                      \
-    case 4: MACRO(2, CL_GRASS); break;                                                    \
-    case 5: MACRO(2, CL_LAW); break;                                                      \
-    case 6: MACRO(3, CL_GRASS); break;                                                    \
-    case 7: MACRO(3, CL_LAW); break;                                                      \
-    case 8: MACRO(4, CL_GRASS); break;                                                    \
-    case 9: MACRO(4, CL_LAW); break;                                                      \
-    case 10: MACRO(5, CL_GRASS); break;                                                   \
-    case 11: MACRO(5, CL_LAW); break;                                                     \
+    switch ((G) * 8 + (CL)) {                                                             \
+    case 8: MACRO(1, CL_GRASS); break;                                                \
+    case 9: MACRO(1, CL_GRASS_THR); break;                                            \
+    case 10: MACRO(1, CL_POWER); break;                                               \
+    case 11: MACRO(1, CL_MPM); break;                                                 \
+    case 12: MACRO(1, CL_VANRIJN); break;                                             \
+    case 16: MACRO(2, CL_GRASS); break;                                               \
+    case 17: MACRO(2, CL_GRASS_THR); break;                                           \
+    case 18: MACRO(2, CL_POWER); break;                                               \
+    case 19: MACRO(2, CL_MPM); break;                                                 \
+    case 20: MACRO(2, CL_VANRIJN); break;                                             \
+    case 24: MACRO(3, CL_GRASS); break;                                               \
+    case 25: MACRO(3, CL_GRASS_THR); break;                                           \
+    case 26: MACRO(3, CL_POWER); break;                                               \
+    case 27: MACRO(3, CL_MPM); break;                                                 \
+    case 28: MACRO(3, CL_VANRIJN); break;                                             \
+    case 32: MACRO(4, CL_GRASS); break;                                               \
+    case 33: MACRO(4, CL_GRASS_THR); break;                                           \
+    case 34: MACRO(4, CL_POWER); break;                                               \
+    case 35: MACRO(4, CL_MPM); break;                                                 \
+    case 36: MACRO(4, CL_VANRIJN); break;                                             \
+    case 40: MACRO(5, CL_GRASS); break;                                               \
+    case 41: MACRO(5, CL_GRASS_THR); break;                                           \
+    case 42: MACRO(5, CL_POWER); break;                                               \
+    case 43: MACRO(5, CL_MPM); break;                                                 \
+    case 44: MACRO(5, CL_VANRIJN); break;                                             \
+    default: return hipErrorInvalidValue;                                                 \
+    }
+
+// Dispatch over the closure alone.
+#define DSVE_DISPATCH_CL(CL, MACRO)                                                       \
+    switch (CL) {                                                                         \
+    case CL_GRASS: MACRO(CL_GRASS); break;                                                \
+    case CL_GRASS_THR: MACRO(CL_GRASS_THR); break;                                        \
+    case CL_POWER: MACRO(CL_POWER); break;                                                \
+    case CL_MPM: MACRO(CL_MPM); break;                                                    \
+    case CL_VANRIJN: MACRO(CL_VANRIJN); break;                                            \
     default: return hipErrorInvalidValue;                                                 \
     }
 
@@ -512,24 +539,23 @@ hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile
                                             : launch_step_w<false>(a, precision, G, cl, tile, grid, stream);
 }
 
+template <int PREC>
+static hipError_t launch_cfl_prec(const CflArgs &a, int cl, hipStream_t stream)
+{
+    const dim3 grid(cfl_grid(a.n_cells)), block(256);
+#define DSVE_LAUNCH_CFL(CC) hipLaunchKernelGGL((k_cfl<PREC, CC>), grid, block, 0, stream, a)
+    DSVE_DISPATCH_CL(cl, DSVE_LAUNCH_CFL)
+#undef DSVE_LAUNCH_CFL
+    return hipGetLastError();
+}
+
 hipError_t launch_cfl(const CflArgs &a, int precision, int cl, hipStream_t stream)
 {
     if (a.n_cells < 1) return hipErrorInvalidValue;
-    const dim3 grid(cfl_grid(a.n_cells)), block(256);
-    if (cl != CL_GRASS && cl != CL_LAW) return hipErrorInvalidValue;
-    if (precision == PREC_FP64) {
-        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_FP64, CL_GRASS>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_cfl<PREC_FP64, CL_LAW>), grid, block, 0, stream, a);
-    } else if (precision == PREC_MIXED) {
-        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_GRASS>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_cfl<PREC_MIXED, CL_LAW>), grid, block, 0, stream, a);
-    } else if (precision == PREC_DOT) {
-        if (cl == CL_GRASS) hipLaunchKernelGGL((k_cfl<PREC_DOT, CL_GRASS>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_cfl<PREC_DOT, CL_LAW>), grid, block, 0, stream, a);
-    } else {
-        return hipErrorNotSupported;
-    }
-    return hipGetLastError();
+    if (precision == PREC_FP64) return launch_cfl_prec<PREC_FP64>(a, cl, stream);
+    if (precision == PREC_MIXED) return launch_cfl_prec<PREC_MIXED>(a, cl, stream);
+    if (precision == PREC_DOT) return launch_cfl_prec<PREC_DOT>(a, cl, stream);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_fluct(const FluctArgs &a, int precision, int G, int cl, hipStream_t stream)

@@ -186,31 +186,27 @@ __device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
 __device__ __forceinline__ double m_rcp(double a) { return rcp_h(a); }
 __device__ __forceinline__ float m_rcp(float a) { return 1.0f / a; }
 
-// b = xi dq_s/dq of a closure at the state (h, q), invh = 1/h (constants lp0, lp1 of the law
-// as laid out in ChanInfo).  Below a law's threshold, and at rest, b = 0.
-template <typename T>
-__device__ __forceinline__ T law_b(int law, T lp0, T lp1, T h, T q, T invh)
+// b = xi dq_s/dq of the closure CL at the state (h, q), invh = 1/h (constants lp0, lp1 of the
+// law as laid out in ChanInfo).  Below a law's threshold, and at rest, b = 0.
+template <int CL, typename T>
+__device__ __forceinline__ T law_b(T lp0, T lp1, T h, T q, T invh)
 {
     const T u = q * invh;
     const T au = m_abs(u);
-    switch (law) {
-    case LAW_GRASS:
+    if constexpr (CL == CL_GRASS) {
         return lp0 * (u * u) * invh;
-    case LAW_GRASS_THR: {
+    } else if constexpr (CL == CL_GRASS_THR) {
         const T ex = au - lp1;
         return ex > T(0) ? lp0 * (ex * ex) * invh : T(0);
-    }
-    case LAW_POWER:
+    } else if constexpr (CL == CL_POWER) {
         return au > T(0) ? lp0 * m_pow(au, lp1) * invh : T(0);
-    case LAW_MPM: {
+    } else if constexpr (CL == CL_MPM) {
         const T th = lp0 * (u * u) * m_rcp(m_cbrt(h));              // Shields stress
         return th > T(0.047) ? lp1 * m_sqrt(th - T(0.047)) * th * m_rcp(m_abs(q)) : T(0);
-    }
-    default: {
+    } else {
         const T tp1 = lp0 * (u * u) * m_rcp(m_cbrt(h));             // u_*^2 / u_*cr^2
         const T tt = tp1 - T(1);
         return tt > T(0) ? lp1 * m_pow(tt, T(1.1)) * tp1 * m_rcp(m_abs(q)) : T(0);
-    }
     }
 }
 
@@ -227,8 +223,8 @@ __device__ __forceinline__ void cubic_params(const Closure &K, T h, T q, T g, T 
         kFr = Fr;
     } else {
         const T invh = g * (inv_c * inv_c);   // c^2 = g h
-        b = law_b<T>(K.law, T(K.lp0), T(K.lp1), h, q, invh);
-        const bool stress = K.law >= LAW_MPM;
+        b = law_b<CL, T>(T(K.lp0), T(K.lp1), h, q, invh);
+        constexpr bool stress = CL >= CL_MPM;
         const T kk = stress ? T(-13.5) : T(-9);   // 18 - 27 kappa
         k1 = fma(T(3), b, fma(Fr, Fr, T(3)));
         k2 = Fr * fma(kk, b, fma(T(-2) * Fr, Fr, T(18)));

@@ -117,10 +117,13 @@ def test_cfl_reduce_mixed(torch_dev, dsve):
     ctx.close()
 
 
-def _sampled_channels_check(dsve, wl, precision, tol, every):
+def _sampled_channels_check(dsve, wl, precision, tol, every, launch=None):
     ctx = dsve.Context.from_workload(wl, precision=precision)
     h, q, z, t = dsve.upload(wl)
-    ctx.autotune(h, q, z, trial_steps=20)   # the launch the benchmark times
+    if launch is None:
+        ctx.autotune(h, q, z, trial_steps=20)   # the launch the benchmark times
+    else:
+        ctx.set_launch(*launch)
     ctx.adot_step(h, q, z, wl.steps, t)
     ctx.sync()
     got = to_np(h, q, z, t)
@@ -148,3 +151,11 @@ def test_full_size_c5_mixed_sampled_channels(torch_dev, dsve):
     wl = inputs.make_c5()
     wl.steps = 300
     _sampled_channels_check(dsve, wl, "mixed", 1e-5, every=2048)
+
+
+def test_wide_index_path_sampled_channels(torch_dev, dsve):
+    # 2^14 channels of 2^15 cells: 2^29 cells and 2^29 + 2^14 edges, past the range of the
+    # step kernel's 32-bit indexing, so the 64-bit form runs; 3 steps, 8 channels checked
+    wl = inputs.make_c4(n_channels=16384, len_lo=32768, len_hi=32768, steps=3)
+    assert wl.n_cells + wl.n_channels >= 2 ** 29
+    _sampled_channels_check(dsve, wl, "fp64", 1e-12, every=2048, launch=(256, 32, 0))
