@@ -184,6 +184,10 @@ static dsve_status build_tile_table(dsve_ctx *c, int tile)
 
 static dsve_status setup(dsve_ctx *c, void *stream)
 {
+    // the power law with an integer exponent beta - 1 in every channel runs the product form
+    if (c->cl == CL_POWER &&
+        std::all_of(c->h_ch.begin(), c->h_ch.end(), [](const ChanInfo &k) { return k.ipow >= 0; }))
+        c->cl = CL_POWER_INT;
     HIP_TRY(c, hipGetDevice(&c->device));
     hipDeviceProp_t prop;
     HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
@@ -266,6 +270,7 @@ static ChanInfo make_chan(int64_t cell0, int64_t n, int law, const dsve_channel 
     }
     ci.fric = ch.ks > 0.0 ? 1.0 / (ch.ks * ch.ks) : 0.0;
     ci.law = law;
+    ci.ipow = -1;
     const double *x = ch.law_extra;
     switch (law) {
     case DSVE_LAW_GRASS:
@@ -278,6 +283,7 @@ static ChanInfo make_chan(int64_t cell0, int64_t n, int law, const dsve_channel 
     case DSVE_LAW_POWER:
         ci.lp0 = xi * ch.A_g * x[0];
         ci.lp1 = x[0] - 1.0;
+        if (ci.lp1 == std::rint(ci.lp1) && ci.lp1 >= 0.0 && ci.lp1 <= 15.0) ci.ipow = (int32_t)ci.lp1;
         break;
     case DSVE_LAW_MPM: {
         const double d50 = x[0], sg1 = x[1] - 1.0;

@@ -34,8 +34,10 @@ enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN
 // Kernel variants by closure, one per law: the Grass law in closed non-dimensional form
 // (CL_GRASS), and each other law through the per-state coefficient b = xi dq_s/dq.  A context
 // has one law, so its kernels are compiled for that law alone.
+// CL_POWER_INT is the power law with an integer exponent beta - 1 in [0, 15] in every channel
+// (then |u|^(beta - 1) is a short product instead of a general power).
 enum { CL_GRASS = LAW_GRASS, CL_GRASS_THR = LAW_GRASS_THR, CL_POWER = LAW_POWER, CL_MPM = LAW_MPM,
-       CL_VANRIJN = LAW_VANRIJN, kNumClosures = 5 };
+       CL_VANRIJN = LAW_VANRIJN, CL_POWER_INT = 5, kNumClosures = 6 };
 
 constexpr int kMaxGauss = 5;
 constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most
@@ -67,7 +69,8 @@ constexpr int step_min_waves(int prec, int cl)
 // Law constants lp0, lp1 (b = xi dq_s/dq at a state with u = q/h, 1/h, |q|):
 //   GRASS      lp0 = 3 xi A_g                        b = lp0 u^2 / h
 //   GRASS_THR  lp0 = 3 xi A_g, lp1 = u_cr            b = lp0 (|u| - u_cr)^2 / h above u_cr
-//   POWER      lp0 = xi A_g beta, lp1 = beta - 1     b = lp0 |u|^lp1 / h
+//   POWER      lp0 = xi A_g beta, lp1 = beta - 1     b = lp0 |u|^lp1 / h  (ipow = lp1 when it
+//                                                    is an integer in [0, 15], else -1)
 //   MPM        lp0 = 1 / (K_s^2 (S_g-1) d50),        theta = lp0 u^2 / h^(1/3),
 //              lp1 = 24 xi sqrt(g (S_g-1) d50^3)     b = lp1 sqrt(theta - 0.047) theta / |q|
 //   VANRIJN    lp0 = g / (K_s^2 u_*cr^2),            T + 1 = lp0 u^2 / h^(1/3),
@@ -88,7 +91,7 @@ struct alignas(16) ChanInfo {
     double bl[4], br[4];
     int32_t bcl, bcr;
     int32_t law;
-    int32_t pad;
+    int32_t ipow;    // power law: integer exponent beta - 1 in [0, 15], else -1
 };
 static_assert(sizeof(ChanInfo) == 160, "ChanInfo layout changed");
 

@@ -439,26 +439,31 @@ static inline unsigned int cfl_grid(int64_t n_cells)
     case 10: MACRO(1, CL_POWER); break;                                               \
     case 11: MACRO(1, CL_MPM); break;                                                 \
     case 12: MACRO(1, CL_VANRIJN); break;                                             \
+    case 13: MACRO(1, CL_POWER_INT); break;                                           \
     case 16: MACRO(2, CL_GRASS); break;                                               \
     case 17: MACRO(2, CL_GRASS_THR); break;                                           \
     case 18: MACRO(2, CL_POWER); break;                                               \
     case 19: MACRO(2, CL_MPM); break;                                                 \
     case 20: MACRO(2, CL_VANRIJN); break;                                             \
+    case 21: MACRO(2, CL_POWER_INT); break;                                           \
     case 24: MACRO(3, CL_GRASS); break;                                               \
     case 25: MACRO(3, CL_GRASS_THR); break;                                           \
     case 26: MACRO(3, CL_POWER); break;                                               \
     case 27: MACRO(3, CL_MPM); break;                                                 \
     case 28: MACRO(3, CL_VANRIJN); break;                                             \
+    case 29: MACRO(3, CL_POWER_INT); break;                                           \
     case 32: MACRO(4, CL_GRASS); break;                                               \
     case 33: MACRO(4, CL_GRASS_THR); break;                                           \
     case 34: MACRO(4, CL_POWER); break;                                               \
     case 35: MACRO(4, CL_MPM); break;                                                 \
     case 36: MACRO(4, CL_VANRIJN); break;                                             \
+    case 37: MACRO(4, CL_POWER_INT); break;                                           \
     case 40: MACRO(5, CL_GRASS); break;                                               \
     case 41: MACRO(5, CL_GRASS_THR); break;                                           \
     case 42: MACRO(5, CL_POWER); break;                                               \
     case 43: MACRO(5, CL_MPM); break;                                                 \
     case 44: MACRO(5, CL_VANRIJN); break;                                             \
+    case 45: MACRO(5, CL_POWER_INT); break;                                           \
     default: return hipErrorInvalidValue;                                                 \
     }
 
@@ -470,6 +475,7 @@ static inline unsigned int cfl_grid(int64_t n_cells)
     case CL_POWER: MACRO(CL_POWER); break;                                                \
     case CL_MPM: MACRO(CL_MPM); break;                                                    \
     case CL_VANRIJN: MACRO(CL_VANRIJN); break;                                            \
+    case CL_POWER_INT: MACRO(CL_POWER_INT); break;                                        \
     default: return hipErrorInvalidValue;                                                 \
     }
 

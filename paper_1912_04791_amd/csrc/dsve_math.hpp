@@ -160,15 +160,35 @@ __device__ __forceinline__ void trisect(double x, double &c, double &s, double &
 struct Closure {
     double kqg, K1, K2;
     double lp0, lp1;
-    int law;
+    int law, ipow;
 };
 __device__ __forceinline__ Closure closure_of(const ChanInfo &ci)
 {
-    return Closure{ci.kqg, ci.K1, ci.K2, ci.lp0, ci.lp1, ci.law};
+    return Closure{ci.kqg, ci.K1, ci.K2, ci.lp0, ci.lp1, ci.law, ci.ipow};
 }
 
 __device__ __forceinline__ double m_pow(double a, double b) { return pow(a, b); }
-__device__ __forceinline__ float m_pow(float a, float b) { return powf(a, b); }
+// FP32 power of the mixed form, a >= 0, b > 0: 2^(b log2 a) from the hardware base-2 logarithm
+// and exponential (relative error about 1e-6 for the exponents of the laws; a = 0 gives 0)
+__device__ __forceinline__ float m_pow(float a, float b)
+{
+    return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(a));
+}
+// a^n, n in [0, 15], as a product of a, a^2, a^4, a^8
+template <typename T>
+__device__ __forceinline__ T ipow15(T a, int n)
+{
+    const T a2 = a * a, a4 = a2 * a2, a8 = a4 * a4;
+    T r = (n & 1) ? a : T(1);
+    r = (n & 2) ? r * a2 : r;
+    r = (n & 4) ? r * a4 : r;
+    return (n & 8) ? r * a8 : r;
+}
+// a^1.1 = a a^(1/10), a > 0: the tenth root from an FP32 estimate 2^(log2(a)/10) and two
+// Newton steps for y^10 = a in FP64, y <- (9 y + a / y^9) / 10 (each squares the relative
+// error: about 1e-7 -> 5e-14 -> below FP64 rounding)
+__device__ __forceinline__ double pow_1p1(double a);
+__device__ __forceinline__ float pow_1p1(float a) { return m_pow(a, 1.1f); }
 // cube root of a > 0: FP32 estimate, then one Halley step y (y^3 + 2a) / (2y^3 + a) in FP64
 // (cubic convergence: about 2^-23 -> 2^-69 relative)
 __device__ __forceinline__ double cbrt_h(double a)
@@ -185,12 +205,23 @@ __device__ __forceinline__ double m_abs(double a) { return fabs(a); }
 __device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
 __device__ __forceinline__ double m_rcp(double a) { return rcp_h(a); }
 __device__ __forceinline__ float m_rcp(float a) { return 1.0f / a; }
+__device__ __forceinline__ double pow_1p1(double a)
+{
+    double y = (double)__builtin_amdgcn_exp2f(0.1f * __builtin_amdgcn_logf((float)fmax(a, 1e-30)));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y2 = y * y, y4 = y2 * y2, y9 = y4 * y4 * y;
+        y = fma(0.9, y, (0.1 * a) * rcp_h(y9));
+    }
+    return a * y;
+}
 
 // b = xi dq_s/dq of the closure CL at the state (h, q), invh = 1/h (constants lp0, lp1 of the
 // law as laid out in ChanInfo).  Below a law's threshold, and at rest, b = 0.
 template <int CL, typename T>
-__device__ __forceinline__ T law_b(T lp0, T lp1, T h, T q, T invh)
+__device__ __forceinline__ T law_b(const Closure &K, T h, T q, T invh)
 {
+    const T lp0 = T(K.lp0), lp1 = T(K.lp1);
     const T u = q * invh;
     const T au = m_abs(u);
     if constexpr (CL == CL_GRASS) {
@@ -200,13 +231,15 @@ __device__ __forceinline__ T law_b(T lp0, T lp1, T h, T q, T invh)
         return ex > T(0) ? lp0 * (ex * ex) * invh : T(0);
     } else if constexpr (CL == CL_POWER) {
         return au > T(0) ? lp0 * m_pow(au, lp1) * invh : T(0);
+    } else if constexpr (CL == CL_POWER_INT) {
+        return au > T(0) ? lp0 * ipow15(au, K.ipow) * invh : T(0);
     } else if constexpr (CL == CL_MPM) {
         const T th = lp0 * (u * u) * m_rcp(m_cbrt(h));              // Shields stress
         return th > T(0.047) ? lp1 * m_sqrt(th - T(0.047)) * th * m_rcp(m_abs(q)) : T(0);
     } else {
         const T tp1 = lp0 * (u * u) * m_rcp(m_cbrt(h));             // u_*^2 / u_*cr^2
         const T tt = tp1 - T(1);
-        return tt > T(0) ? lp1 * m_pow(tt, T(1.1)) * tp1 * m_rcp(m_abs(q)) : T(0);
+        return tt > T(0) ? lp1 * pow_1p1(tt) * tp1 * m_rcp(m_abs(q)) : T(0);
     }
 }
 
@@ -223,8 +256,8 @@ __device__ __forceinline__ void cubic_params(const Closure &K, T h, T q, T g, T 
         kFr = Fr;
     } else {
         const T invh = g * (inv_c * inv_c);   // c^2 = g h
-        b = law_b<CL, T>(T(K.lp0), T(K.lp1), h, q, invh);
-        constexpr bool stress = CL >= CL_MPM;
+        b = law_b<CL, T>(K, h, q, invh);
+        constexpr bool stress = CL == CL_MPM || CL == CL_VANRIJN;
         const T kk = stress ? T(-13.5) : T(-9);   // 18 - 27 kappa
         k1 = fma(T(3), b, fma(Fr, Fr, T(3)));
         k2 = Fr * fma(kk, b, fma(T(-2) * Fr, Fr, T(18)));

@@ -19,7 +19,8 @@ pytestmark = pytest.mark.gpu
 
 LAWS = {   # law, A_g, parameters, K_s  (the same values as the oracle's closure pins)
     "grass_thr": (oracle.LAW_GRASS_THR, 0.0024, (0.3,), 0.0),
-    "power": (oracle.LAW_POWER, 1.45e-3, (5.0,), 0.0),
+    "power": (oracle.LAW_POWER, 1.45e-3, (5.0,), 0.0),        # integer beta - 1: product form
+    "power_real": (oracle.LAW_POWER, 1.45e-3, (2.5,), 0.0),   # general power
     "mpm": (oracle.LAW_MPM, 0.0, (3.2e-4, 2.6), 49.4),
     "vanrijn": (oracle.LAW_VANRIJN, 0.0, (3.2e-4, 2.6, 1e-6, 0.03), 62.0),
 }
