@@ -186,7 +186,7 @@ __device__ __forceinline__ T ipow15(T a, int n)
 }
 // a^1.1 = a a^(1/10), a > 0: the tenth root from an FP32 estimate 2^(log2(a)/10) and two
 // Newton steps for y^10 = a in FP64, y <- (9 y + a / y^9) / 10 (each squares the relative
-// error: about 1e-7 -> 5e-14 -> below FP64 rounding)
+// error: about 4e-7 -> 7e-13 -> the rounding of y^9, a few ulp)
 __device__ __forceinline__ double pow_1p1(double a);
 __device__ __forceinline__ float pow_1p1(float a) { return m_pow(a, 1.1f); }
 // cube root of a > 0: FP32 estimate, then one Halley step y (y^3 + 2a) / (2y^3 + a) in FP64

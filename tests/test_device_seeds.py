@@ -97,3 +97,30 @@ def test_gap_product_identity():
     src = open(HDR).read()
     val = float(re.search(r"kInvGapScale = ([0-9.]+);", src).group(1))
     assert abs(val - 1.5 * np.sqrt(3)) < 1e-15
+
+
+def test_tenth_root_newton_reaches_fp64():
+    # a^1.1 = a * a^(1/10): FP32 estimate 2^(log2(a)/10) (emulated here with numpy's float32
+    # exp2/log2), then two Newton steps for y^10 = a in FP64, as the Van Rijn closure takes it
+    a = np.concatenate([np.logspace(-15, 3, 20001), np.linspace(0.5, 2.0, 2001)])
+    y = np.exp2(np.float32(0.1) * np.log2(a.astype(np.float32))).astype(np.float64)
+    assert np.max(np.abs(y / a ** 0.1 - 1)) < 1e-6
+    for _ in range(2):
+        y9 = (y * y) ** 2
+        y9 = y9 * y9 * y
+        y = 0.9 * y + (0.1 * a) / y9
+    np.testing.assert_allclose(a * y, a ** 1.1, rtol=5e-15)   # a few ulp: the rounding of y^9
+
+
+def test_integer_power_product():
+    # |u|^n for n in [0, 15] as the product of u, u^2, u^4, u^8 selected by the bits of n
+    u = np.linspace(1e-3, 3.0, 1001)
+    for n in range(16):
+        u2 = u * u
+        u4 = u2 * u2
+        u8 = u4 * u4
+        r = np.where(n & 1, u, 1.0)
+        r = np.where(n & 2, r * u2, r)
+        r = np.where(n & 4, r * u4, r)
+        r = np.where(n & 8, r * u8, r)
+        np.testing.assert_allclose(r, u ** n, rtol=4 * 2.2e-16 * max(n, 1))
