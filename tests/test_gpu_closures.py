@@ -21,6 +21,7 @@ LAWS = {   # law, A_g, parameters, K_s  (the same values as the oracle's closure
     "grass_thr": (oracle.LAW_GRASS_THR, 0.0024, (0.3,), 0.0),
     "power": (oracle.LAW_POWER, 1.45e-3, (5.0,), 0.0),        # integer beta - 1: product form
     "power_real": (oracle.LAW_POWER, 1.45e-3, (2.5,), 0.0),   # general power
+    "power_b2": (oracle.LAW_POWER, 4e-3, (2.0,), 0.0),        # beta - 1 = 1: the lowest bit
     "mpm": (oracle.LAW_MPM, 0.0, (3.2e-4, 2.6), 49.4),
     "vanrijn": (oracle.LAW_VANRIJN, 0.0, (3.2e-4, 2.6, 1e-6, 0.03), 62.0),
 }
