@@ -46,15 +46,41 @@ def ops_per_edge_update(G: int = 3) -> int:
     return G * OPS_PER_NODE + OPS_PER_CELL
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and whitespace (string literals kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the code (comments and whitespace removed) of the kernel sources and the
+    build flags: a counter summary stays valid across edits that change no code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_04791_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
-    with open(os.path.join(ROOT, "paper_1912_04791_amd", "build.py"), "rb") as f:
-        h.update(f.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
+                h.update(_code_only(f.read()).encode())
+    with open(os.path.join(ROOT, "paper_1912_04791_amd", "build.py"), encoding="utf-8") as f:
+        h.update(f.read().encode())
     return h.hexdigest()[:16]
 
 

@@ -3,7 +3,8 @@
 // k_step      one fused kernel per time step over the flat edge space of all channels:
 //             ghost cells (boundary conditions), DOT fluctuation of every edge, exchange of
 //             D^- through LDS, cell update into the other ping-pong buffer, CFL speed of the
-//             new state reduced per channel (wave shuffles -> LDS -> one global atomic max).
+//             new state reduced per channel (DPP lane moves -> LDS -> one global atomic max
+//             per workgroup into its CFL sub-slot).
 // k_cfl       CFL maximum of a state (start of a run, and the cfl_reduce entry point).
 // k_fluct     pairwise fluctuations (dot_edge_fluct entry point).
 // k_update    cell update from given fluctuations (cell_update entry point).

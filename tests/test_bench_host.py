@@ -1,0 +1,31 @@
+"""Host-side logic of bench.py: the kernel-source hash that keys the committed counter
+summaries ignores comments and whitespace, and a summary taken on other code is not used."""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_code_only_drops_comments_and_whitespace_but_keeps_strings():
+    a = 'int a = 1; // note\n/* block\n comment */ const char *s = "x // y /* z */";\n'
+    b = 'int a=1;const char*s="x // y /* z */";'
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only("int a = 1;") != bench._code_only("int a = 2;")
+
+
+def test_traffic_is_used_only_for_the_current_code(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    ok = {"kernel_hash": bench.kernel_source_hash(), "bytes_per_launch": 1.0e6}
+    stale = {"kernel_hash": "0" * 16, "bytes_per_launch": 2.0e6}
+    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ok, "c2:mixed": stale}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the hash itself reads the sources under the real root
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: ok["kernel_hash"])
+    assert bench.measured_traffic("c2", "fp64") == 1.0e6
+    assert bench.measured_traffic("c2", "mixed") is None
+    assert bench.measured_traffic("c3", "fp64") is None
