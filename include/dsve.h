@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DSVE_ABI_VERSION 3
+#define DSVE_ABI_VERSION 4
 
 typedef struct dsve_ctx dsve_ctx;
 
@@ -250,6 +250,17 @@ dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, 
 dsve_status dsve_set_cfl_split(dsve_ctx *ctx, int split);
 dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split);
 
+/* Channel-resident runs (Sec. 3, Eq. scheme, run step after step on chip): when every
+ * channel of the context has at most 255 cells, adot_step / adot_step_batched by default
+ * run all n steps in one launch, one workgroup per channel at a time, with the state on
+ * chip and each channel's CFL maximum reduced within its workgroup.  The results are
+ * bitwise those of the per-step kernels; the per-step launch latency, which bounds such
+ * small problems, is paid once.  mode 0: automatic (resident when eligible); 1: always
+ * per-step kernels.  The launch configuration and CFL sub-slots do not apply to resident
+ * runs.  dsve_get_resident reports whether the next run will be resident. */
+dsve_status dsve_set_resident(dsve_ctx *ctx, int mode);
+dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active);
+
 /* Autotuner: time candidate (tile, blocks_per_cu) pairs for `trial_steps`
  * fused steps each (rounded up to whole replays of a 12-step graph, after one warm-up
  * replay that captures it, when the context uses graphs) on a scratch copy of (h, q, z),
@@ -257,7 +268,7 @@ dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split);
  * fastest with 1 and with 4 CFL sub-slots -- the caller's arrays are read, never written
  * -- and keep the fastest in the context.  If cache_path is not NULL, a JSON cache keyed
  * by device, precision, law and problem shape is read first and updated after tuning.
- * Waits for completion. */
+ * Does nothing when the context's runs are channel-resident.  Waits for completion. */
 dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
                           int trial_steps, const char *cache_path);
 

@@ -51,6 +51,8 @@ struct dsve_ctx {
     int64_t amax_cs = 0;                                         // Cs (sub-slot stride)
     int64_t amax_slot = 0;                                       // kAmaxSplitMax * Cs (one slot)
     int cfl_split = 0;                                           // CFL sub-slots; 0 = automatic
+    bool resident_ok = false;    // every channel has at most kResidentCells cells
+    int resident_mode = 0;       // 0: channel-resident runs when resident_ok; 1: never
     unsigned int *d_flags = nullptr;                             // [4]
 
     int tile = 256, blocks_per_cu = 0, graph_steps = 60;
@@ -200,6 +202,9 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     c->h_eoff.resize(C + 1);
     for (int64_t k = 0; k <= C; ++k) c->h_eoff[k] = c->h_off[k] + k;
     c->n_edges = c->h_eoff[C];
+    c->resident_ok = true;
+    for (int64_t k = 0; k < C; ++k)
+        if (c->h_off[k + 1] - c->h_off[k] > kResidentCells) c->resident_ok = false;
     HIP_TRY(c, hipMalloc(&c->d_ch, sizeof(ChanInfo) * C));
     HIP_TRY(c, hipMalloc(&c->d_off, sizeof(int64_t) * (C + 1)));
     HIP_TRY(c, hipMalloc(&c->d_eoff, sizeof(int64_t) * (C + 1)));
@@ -578,6 +583,21 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
     if (!h || !q || !z || !t) return fail(ctx, DSVE_E_ARG, "null pointer");
     if (n_steps < 0) return fail(ctx, DSVE_E_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return DSVE_OK;
+    if (ctx->resident_ok && ctx->resident_mode == 0) {
+        // short channels: the whole run in one launch, one workgroup per channel at a time;
+        // the final CFL maximum lands in sub-slot 0 of slot 0 for the check in dsve_sync
+        HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, 3 * ctx->amax_slot, 0ull, ctx->stream));
+        ResidentArgs a{};
+        a.h = h; a.q = q; a.z = z; a.t = t;
+        a.ch = ctx->d_ch; a.off = ctx->d_off; a.amax = ctx->d_amax; a.flags = ctx->d_flags;
+        a.n_channels = (int32_t)ctx->n_channels;
+        a.n_steps = n_steps;
+        a.g = ctx->g;
+        const int grid = (int)std::min<int64_t>(ctx->n_channels, (int64_t)8 * ctx->cus);
+        HIP_TRY(ctx, launch_resident(a, ctx->precision, ctx->G, ctx->cl, grid, ctx->stream));
+        ctx->last_amax_slot = 0;
+        return DSVE_OK;
+    }
     dsve_status st = build_tile_table(ctx, ctx->tile);
     if (st != DSVE_OK) return st;
     // slots: clear all three, CFL max of W^0 into sub-slot 0 of slot 0
@@ -691,6 +711,21 @@ dsve_status dsve_set_cfl_split(dsve_ctx *ctx, int split)
     return DSVE_OK;
 }
 
+dsve_status dsve_set_resident(dsve_ctx *ctx, int mode)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (mode != 0 && mode != 1) return fail(ctx, DSVE_E_ARG, "resident mode must be 0 or 1");
+    ctx->resident_mode = mode;
+    return DSVE_OK;
+}
+
+dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active)
+{
+    if (!ctx || !active) return DSVE_E_ARG;
+    *active = (ctx->resident_ok && ctx->resident_mode == 0) ? 1 : 0;
+    return DSVE_OK;
+}
+
 dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split)
 {
     if (!ctx || !split) return DSVE_E_ARG;
@@ -767,6 +802,8 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     if (ctx->sticky != DSVE_OK) return ctx->sticky;
     if (!h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
     if (trial_steps < 2 || trial_steps > 1000) return fail(ctx, DSVE_E_ARG, "trial_steps must be in [2, 1000]");
+    // a channel-resident run has no launch configuration to tune
+    if (ctx->resident_ok && ctx->resident_mode == 0) return DSVE_OK;
     const std::string key = tune_key(ctx);
     int tile = 0, bpc = 0, split = 0;
     if (cache_lookup(cache_path, key, tile, bpc, split)) {

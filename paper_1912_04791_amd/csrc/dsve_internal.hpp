@@ -152,6 +152,23 @@ struct StepArgs {
     double g;
 };
 
+// Channel-resident runs: every channel of at most kResidentCells cells is held by one
+// workgroup of kResidentCells + 1 threads (one edge and one cell each) for all steps of a run,
+// with its state in registers and LDS, so the run is one launch.
+constexpr int kResidentCells = 255;
+
+struct ResidentArgs {
+    double *h, *q, *z;           // state, updated in place
+    double *t;                   // [C] clocks
+    const ChanInfo *ch;
+    const int64_t *off;          // [C+1] cell offsets
+    unsigned long long *amax;    // [C] CFL maximum of the final state (bit patterns)
+    unsigned int *flags;
+    int32_t n_channels;
+    int32_t n_steps;
+    double g;
+};
+
 struct CflArgs {
     const double *h, *q, *z;
     const ChanInfo *ch;
@@ -193,6 +210,9 @@ hipError_t launch_dt(const unsigned long long *amax, const ChanInfo *ch, int32_t
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream_t stream);
+// All n_steps of a run of channels of at most kResidentCells cells in one launch.
+hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int grid,
+                           hipStream_t stream);
 // kAmaxSplitMax as compiled into the kernels (the host code checks it against its own).
 int amax_split_of_kernels();
 

@@ -313,6 +313,110 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
 }
 
 // ---------------------------------------------------------------------------
+// Maximum over the workgroup (uniform result): wave maxima through LDS.  `s_w` holds one entry
+// per wave; consecutive calls are separated by at least one other barrier of the caller.
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v, unsigned long long *s_w)
+{
+    const unsigned long long m = wave_max_u64(v);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = m;
+    __syncthreads();
+    unsigned long long r = 0ull;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) r = (s_w[w] > r) ? s_w[w] : r;
+    return r;
+}
+
+// Channel-resident run: one workgroup takes one channel of N <= kResidentCells cells (thread i
+// holds cell i and computes edge i, between cells i-1 and i) through all n steps of the run,
+// with the state in registers, the neighbour states and D^- exchanged through LDS, and the
+// channel's CFL maximum reduced within the workgroup; then the next channel.  Every value is
+// computed as in k_step (same fluctuation, update and speed, same order of operations), so the
+// results are bitwise those of the per-step kernels.
+template <int G, int PREC, int CL>
+__global__ __launch_bounds__(kResidentCells + 1, step_min_waves(PREC, CL) < 3 ? step_min_waves(PREC, CL) : 3)
+void k_resident(ResidentArgs A)
+{
+    __shared__ double s_st[3][kResidentCells + 1];    // h, q, z of the cells
+    __shared__ double s_dm[3][kResidentCells + 2];    // D^- of the edges
+    __shared__ unsigned long long s_w[(kResidentCells + 64) / 64];
+    const int t = threadIdx.x;
+    bool bad = false;
+    for (int c = blockIdx.x; c < A.n_channels; c += gridDim.x) {
+        const ChanInfo ci = A.ch[c];
+        const Closure K = closure_of(ci);
+        const int64_t cell0 = A.off[c];
+        const int N = (int)(A.off[c + 1] - cell0);
+        const bool has_cell = t < N, has_edge = t <= N;
+        double h = 0.0, q = 0.0, z = 0.0;
+        if (has_cell) {
+            h = A.h[cell0 + t];
+            q = A.q[cell0 + t];
+            z = A.z[cell0 + t];
+        }
+        double tc = A.t[c];
+        unsigned long long sp = 0ull;
+        if (has_cell) sp = (unsigned long long)__double_as_longlong(fabs(cell_speed<PREC, CL>(h, q, A.g, K, bad)));
+        unsigned long long amax_bits = block_max_u64(sp, s_w);
+        for (int n = 0; n < A.n_steps; ++n) {
+            const double dt = ci.cfl_dx * rcp_h(__longlong_as_double((long long)amax_bits));
+            const double r = dt * ci.inv_dx;
+            if (has_cell) {
+                s_st[0][t] = h;
+                s_st[1][t] = q;
+                s_st[2][t] = z;
+            }
+            __syncthreads();
+            double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
+            if (has_edge) {
+                const int il = (t == 0) ? (ci.bcl == BC_PERIODIC ? N - 1 : 0) : t - 1;
+                const int ir = (t == N) ? (ci.bcr == BC_PERIODIC ? 0 : N - 1) : t;
+                double hL = s_st[0][il], qL = s_st[1][il], zL = s_st[2][il];
+                double hR = s_st[0][ir], qR = s_st[1][ir], zR = s_st[2][ir];
+                if (t == 0) {
+                    hL = ghost_h(ci.bcl, ci.bl, hL);
+                    qL = ghost_q(ci.bcl, ci.bl, qL);
+                    if (ci.bcl == BC_DIRICHLET) zL = ghost_z(ci.bcl, ci.bl, zL, tc);
+                } else if (t == N) {
+                    hR = ghost_h(ci.bcr, ci.br, hR);
+                    qR = ghost_q(ci.bcr, ci.br, qR);
+                    if (ci.bcr == BC_DIRICHLET) zR = ghost_z(ci.bcr, ci.br, zR, tc);
+                }
+                edge_fluct<G, PREC, CL>(hL, qL, zL, hR, qR, zR, A.g, K, Dm, Dp, bad);
+                s_dm[0][t] = Dm[0];
+                s_dm[1][t] = Dm[1];
+                s_dm[2][t] = Dm[2];
+            }
+            __syncthreads();
+            sp = 0ull;
+            if (has_cell) {
+                // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i^n) (Sec. 3, Eq. scheme)
+                const double hn = h - r * (s_dm[0][t + 1] + Dp[0]);
+                double qn = q - r * (s_dm[1][t + 1] + Dp[1]);
+                const double zn = z - r * (s_dm[2][t + 1] + Dp[2]);
+                if (ci.fric > 0.0) qn = fma(dt, friction_source(h, q, A.g, ci.fric), qn);
+                h = hn;
+                q = qn;
+                z = zn;
+                sp = (unsigned long long)__double_as_longlong(fabs(cell_speed<PREC, CL>(h, q, A.g, K, bad)));
+            }
+            amax_bits = block_max_u64(sp, s_w);
+            tc += dt;
+        }
+        if (has_cell) {
+            A.h[cell0 + t] = h;
+            A.q[cell0 + t] = q;
+            A.z[cell0 + t] = z;
+        }
+        if (t == 0) {
+            A.t[c] = tc;
+            A.amax[c] = amax_bits;
+        }
+        __syncthreads();   // the next channel reuses the LDS
+    }
+    raise_flag(A.flags, bad);
+}
+
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int find_channel(const int64_t *off, int C, int64_t i)
 {
     int lo = 0, hi = C;   // off[lo] <= i < off[hi]
@@ -603,6 +707,26 @@ hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_resident_prec(const ResidentArgs &a, int G, int cl, int grid, hipStream_t s)
+{
+#define DSVE_LAUNCH_RES(GG, CC) hipLaunchKernelGGL((k_resident<GG, PREC, CC>), dim3(grid), \
+                                                   dim3(kResidentCells + 1), 0, s, a)
+    DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_RES)
+#undef DSVE_LAUNCH_RES
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int grid,
+                           hipStream_t stream)
+{
+    if (grid < 1 || a.n_channels < 1 || a.n_steps < 1) return hipErrorInvalidValue;
+    if (precision == PREC_FP64) return launch_resident_prec<PREC_FP64>(a, G, cl, grid, stream);
+    if (precision == PREC_MIXED) return launch_resident_prec<PREC_MIXED>(a, G, cl, grid, stream);
+    if (precision == PREC_DOT) return launch_resident_prec<PREC_DOT>(a, G, cl, grid, stream);
+    return hipErrorNotSupported;
 }
 
 int amax_split_of_kernels() { return kAmaxSplitMax; }

@@ -112,14 +112,17 @@ lib.dsve_get_launch.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POIN
 lib.dsve_autotune.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_char_p]
 lib.dsve_set_cfl_split.argtypes = [_ctxp, ctypes.c_int]
 lib.dsve_get_cfl_split.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int)]
+lib.dsve_set_resident.argtypes = [_ctxp, ctypes.c_int]
+lib.dsve_get_resident.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int)]
 lib.dsve_device_cus.argtypes = [_ctxp]
 lib.dsve_device_cus.restype = ctypes.c_int
-assert lib.dsve_abi_version() == 3, "libdsve ABI version mismatch"
+assert lib.dsve_abi_version() == 4, "libdsve ABI version mismatch"
 
 ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destroy",
                 "dot_edge_fluct", "cell_update", "cfl_reduce", "adot_step", "adot_step_batched",
                 "dsve_sync", "dsve_last_error", "dsve_clear_error", "dsve_set_launch",
-                "dsve_get_launch", "dsve_set_cfl_split", "dsve_get_cfl_split", "dsve_autotune",
+                "dsve_get_launch", "dsve_set_cfl_split", "dsve_get_cfl_split", "dsve_set_resident",
+                "dsve_get_resident", "dsve_autotune",
                 "dsve_device_cus")
 
 
@@ -323,6 +326,15 @@ class Context:
         v = ctypes.c_int()
         self._check(lib.dsve_get_cfl_split(self._h, ctypes.byref(v)), "dsve_get_cfl_split")
         return v.value
+
+    def set_resident(self, mode: int):
+        """0: channel-resident runs when every channel has at most 255 cells; 1: never."""
+        self._check(lib.dsve_set_resident(self._h, mode), "dsve_set_resident")
+
+    def get_resident(self) -> bool:
+        v = ctypes.c_int()
+        self._check(lib.dsve_get_resident(self._h, ctypes.byref(v)), "dsve_get_resident")
+        return bool(v.value)
 
     def autotune(self, h, q, z, trial_steps: int = 10, cache_path: str | None = None):
         cp = cache_path.encode() if cache_path else None
