@@ -257,7 +257,9 @@ dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split);
  * bitwise those of the per-step kernels; the per-step launch latency, which bounds such
  * small problems, is paid once.  mode 0: automatic (resident when eligible); 1: always
  * per-step kernels.  The launch configuration and CFL sub-slots do not apply to resident
- * runs.  dsve_get_resident reports whether the next run will be resident. */
+ * runs.  dsve_get_resident reports whether the next run will be resident.  Resident runs
+ * leave lanes idle in channels much shorter than 255 cells; dsve_autotune compares them
+ * with the per-step kernels. */
 dsve_status dsve_set_resident(dsve_ctx *ctx, int mode);
 dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active);
 
@@ -268,7 +270,9 @@ dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active);
  * fastest with 1 and with 4 CFL sub-slots -- the caller's arrays are read, never written
  * -- and keep the fastest in the context.  If cache_path is not NULL, a JSON cache keyed
  * by device, precision, law and problem shape is read first and updated after tuning.
- * Does nothing when the context's runs are channel-resident.  Waits for completion. */
+ * When the context can run channel-resident (and that is not turned off), a resident run
+ * is timed too: it stays on if it is the fastest, else it is turned off (mode 1) for the
+ * context.  Waits for completion. */
 dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
                           int trial_steps, const char *cache_path);
 

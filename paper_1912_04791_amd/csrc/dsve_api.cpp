@@ -755,7 +755,8 @@ static std::string tune_key(const dsve_ctx *ctx)
     return os.str();
 }
 
-static bool cache_lookup(const char *path, const std::string &key, int &tile, int &bpc, int &split)
+static bool cache_lookup(const char *path, const std::string &key, int &tile, int &bpc, int &split,
+                         int &resident)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -772,13 +773,15 @@ static bool cache_lookup(const char *path, const std::string &key, int &tile, in
         bpc = std::atoi(line.c_str() + pb + 17);
         const size_t ps = line.find("\"cfl_split\": ");
         split = ps == std::string::npos ? 0 : std::atoi(line.c_str() + ps + 13);
+        const size_t pr = line.find("\"resident_mode\": ");
+        resident = pr == std::string::npos ? 0 : std::atoi(line.c_str() + pr + 17);
         return true;
     }
     return false;
 }
 
 static void cache_store(const char *path, const std::string &key, int tile, int bpc, int split,
-                        double ms)
+                        int resident, double ms)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -792,7 +795,8 @@ static void cache_store(const char *path, const std::string &key, int tile, int 
     std::ofstream o(path, std::ios::trunc);
     for (auto &l : keep) o << l << "\n";
     o << "{\"key\": \"" << key << "\", \"tile\": " << tile << ", \"blocks_per_cu\": " << bpc
-      << ", \"cfl_split\": " << split << ", \"ms_per_step\": " << ms << "}\n";
+      << ", \"cfl_split\": " << split << ", \"resident_mode\": " << resident
+      << ", \"ms_per_step\": " << ms << "}\n";
 }
 
 extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q,
@@ -802,13 +806,15 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     if (ctx->sticky != DSVE_OK) return ctx->sticky;
     if (!h || !q || !z) return fail(ctx, DSVE_E_ARG, "null pointer");
     if (trial_steps < 2 || trial_steps > 1000) return fail(ctx, DSVE_E_ARG, "trial_steps must be in [2, 1000]");
-    // a channel-resident run has no launch configuration to tune
-    if (ctx->resident_ok && ctx->resident_mode == 0) return DSVE_OK;
-    const std::string key = tune_key(ctx);
-    int tile = 0, bpc = 0, split = 0;
-    if (cache_lookup(cache_path, key, tile, bpc, split)) {
+    // channel-resident runs are timed against the per-step kernels only where the caller
+    // left them on
+    const bool try_resident = ctx->resident_ok && ctx->resident_mode == 0;
+    const std::string key = tune_key(ctx) + (try_resident ? "|res" : "");
+    int tile = 0, bpc = 0, split = 0, resident = ctx->resident_mode;
+    if (cache_lookup(cache_path, key, tile, bpc, split, resident)) {
         dsve_status st = dsve_set_launch(ctx, tile, bpc, ctx->graph_steps);
-        return st != DSVE_OK ? st : dsve_set_cfl_split(ctx, split);
+        if (st == DSVE_OK) st = dsve_set_cfl_split(ctx, split);
+        return st != DSVE_OK ? st : dsve_set_resident(ctx, resident);
     }
 
     const size_t bytes = sizeof(double) * ctx->n_cells;
@@ -857,7 +863,15 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     // (time, tile, blocks per CU, sub-slots); first pass with the automatic sub-slot count
     struct Cand { float ms; int tile, bpc, split; };
     std::vector<Cand> cands;
+    float resident_ms = 1e30f;
+    if (try_resident) {   // one launch for all the trial steps
+        float ms = 0.f;
+        status = trial(ctx->tile, ctx->blocks_per_cu, ctx->cfl_split, ms);
+        if (status == DSVE_OK) resident_ms = ms;
+        ctx->resident_mode = 1;   // the per-step candidates below
+    }
     for (int ti : tiles) {
+        if (status != DSVE_OK) break;
         for (int bi : bpcs) {
             float ms = 0.f;
             status = trial(ti, bi, 0, ms);
@@ -886,13 +900,19 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     (void)hipFree(sq);
     (void)hipFree(sz);
     (void)hipFree(st_);
-    if (status != DSVE_OK) return status;
+    if (status != DSVE_OK) {
+        if (try_resident) ctx->resident_mode = 0;
+        return status;
+    }
     Cand best{1e30f, ctx->tile, ctx->blocks_per_cu, save_split};
     for (const Cand &c : cands)
         if (c.ms < best.ms) best = c;
+    const int mode = (try_resident && resident_ms <= best.ms) ? 0 : (try_resident ? 1 : ctx->resident_mode);
+    if (try_resident) ctx->resident_mode = mode;
     dsve_status st = dsve_set_launch(ctx, best.tile, best.bpc, save_graph);
     if (st == DSVE_OK) st = dsve_set_cfl_split(ctx, best.split);
     if (st != DSVE_OK) return st;
-    cache_store(cache_path, key, best.tile, best.bpc, best.split, best.ms / timed);
+    cache_store(cache_path, key, best.tile, best.bpc, best.split, ctx->resident_mode,
+                std::min(best.ms, resident_ms) / timed);
     return DSVE_OK;
 }

@@ -136,3 +136,26 @@ def test_resident_reports_nonfinite(torch_dev, dsve):
     ctx.adot_step(h, q, z, 5, t)
     assert ctx.sync_status() == dsve.E_NONFINITE
     ctx.close()
+
+
+def test_autotune_chooses_between_resident_and_per_step(torch_dev, dsve, tmp_path):
+    import json
+    wl = inputs.make_c4(n_channels=600, len_lo=20, len_hi=255, steps=24)
+    ref = run(dsve, wl, "fp64", resident=1)
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    cache = str(tmp_path / "tune.json")
+    ctx.autotune(h, q, z, trial_steps=12, cache_path=cache)
+    chosen = ctx.get_resident()
+    entry = json.loads(open(cache).read().splitlines()[0])
+    assert entry["resident_mode"] == (0 if chosen else 1)
+    ctx.adot_step(h, q, z, wl.steps, t)
+    ctx.sync()
+    for x, y in zip((h, q, z, t), ref):
+        assert np.array_equal(x.cpu().numpy(), y)
+    # the cached choice is restored without tuning
+    ctx2 = dsve.Context.from_workload(wl)
+    ctx2.autotune(h, q, z, trial_steps=12, cache_path=cache)
+    assert ctx2.get_resident() == chosen
+    ctx.close()
+    ctx2.close()
