@@ -206,14 +206,16 @@ dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const do
 /* Advance one channel by n_steps >= 0 time steps in place: per step, ghost
  * cells from the boundary conditions, dt = cfl*dx/amax(W^n), DOT fluctuations
  * at every edge, cell update with the friction source, and the CFL speed of W^{n+1} --
- * one fused kernel per step, replayed from a HIP graph.  *t_dev (device) is
+ * one fused kernel per step, replayed from a HIP graph, or one launch for the whole run
+ * when the run is channel-resident (dsve_set_resident).  *t_dev (device) is
  * increased by the sum of the time steps.  The result is in (h, q, z) when the
  * enqueued work completes, bitwise independent of the launch configuration. */
 dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps, double *t_dev);
 
 /* As adot_step for a batched context: h, q, z hold all channels back to back
  * (offsets as given to dsve_batch_init); t_dev[n_channels] receives each
- * channel's clock.  All channels run in one persistent kernel per step. */
+ * channel's clock.  All channels run in one persistent kernel per step, or in one
+ * launch for the whole run when it is channel-resident. */
 dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
                               double *t_dev);
 
