@@ -253,15 +253,16 @@ dsve_status dsve_set_cfl_split(dsve_ctx *ctx, int split);
 dsve_status dsve_get_cfl_split(const dsve_ctx *ctx, int *split);
 
 /* Channel-resident runs (Sec. 3, Eq. scheme, run step after step on chip): when every
- * channel of the context has at most 255 cells, adot_step / adot_step_batched by default
- * run all n steps in one launch, one workgroup per channel at a time, with the state on
- * chip and each channel's CFL maximum reduced within its workgroup.  The results are
+ * channel of the context has at most 511 cells, adot_step / adot_step_batched by default
+ * run all n steps in one launch, one workgroup per channel at a time (256 threads, or 512
+ * when a channel has more than 255 cells), with the state on chip and each channel's CFL
+ * maximum reduced within its workgroup.  The results are
  * bitwise those of the per-step kernels; the per-step launch latency, which bounds such
  * small problems, is paid once.  mode 0: automatic (resident when eligible); 1: always
  * per-step kernels.  The launch configuration and CFL sub-slots do not apply to resident
  * runs.  dsve_get_resident reports whether the next run will be resident.  Resident runs
- * leave lanes idle in channels much shorter than 255 cells; dsve_autotune compares them
- * with the per-step kernels. */
+ * leave lanes idle in channels much shorter than their workgroup; dsve_autotune compares
+ * them with the per-step kernels. */
 dsve_status dsve_set_resident(dsve_ctx *ctx, int mode);
 dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active);
 

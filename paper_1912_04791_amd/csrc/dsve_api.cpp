@@ -52,6 +52,7 @@ struct dsve_ctx {
     int64_t amax_slot = 0;                                       // kAmaxSplitMax * Cs (one slot)
     int cfl_split = 0;                                           // CFL sub-slots; 0 = automatic
     bool resident_ok = false;    // every channel has at most kResidentCells cells
+    int resident_threads = 256;  // workgroup size of resident runs: 256, or 512 past 255 cells
     int resident_mode = 0;       // 0: channel-resident runs when resident_ok; 1: never
     unsigned int *d_flags = nullptr;                             // [4]
 
@@ -202,9 +203,10 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     c->h_eoff.resize(C + 1);
     for (int64_t k = 0; k <= C; ++k) c->h_eoff[k] = c->h_off[k] + k;
     c->n_edges = c->h_eoff[C];
-    c->resident_ok = true;
-    for (int64_t k = 0; k < C; ++k)
-        if (c->h_off[k + 1] - c->h_off[k] > kResidentCells) c->resident_ok = false;
+    int64_t longest = 0;
+    for (int64_t k = 0; k < C; ++k) longest = std::max<int64_t>(longest, c->h_off[k + 1] - c->h_off[k]);
+    c->resident_ok = longest <= kResidentCells;
+    c->resident_threads = longest <= kResidentSmall ? 256 : 512;
     HIP_TRY(c, hipMalloc(&c->d_ch, sizeof(ChanInfo) * C));
     HIP_TRY(c, hipMalloc(&c->d_off, sizeof(int64_t) * (C + 1)));
     HIP_TRY(c, hipMalloc(&c->d_eoff, sizeof(int64_t) * (C + 1)));
@@ -593,8 +595,9 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
         a.n_channels = (int32_t)ctx->n_channels;
         a.n_steps = n_steps;
         a.g = ctx->g;
-        const int grid = (int)std::min<int64_t>(ctx->n_channels, (int64_t)8 * ctx->cus);
-        HIP_TRY(ctx, launch_resident(a, ctx->precision, ctx->G, ctx->cl, grid, ctx->stream));
+        const int grid = (int)std::min<int64_t>(ctx->n_channels, (int64_t)(2048 / ctx->resident_threads) * ctx->cus);
+        HIP_TRY(ctx, launch_resident(a, ctx->precision, ctx->G, ctx->cl, ctx->resident_threads, grid,
+                                     ctx->stream));
         ctx->last_amax_slot = 0;
         return DSVE_OK;
     }

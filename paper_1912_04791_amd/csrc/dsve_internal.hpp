@@ -153,9 +153,11 @@ struct StepArgs {
 };
 
 // Channel-resident runs: every channel of at most kResidentCells cells is held by one
-// workgroup of kResidentCells + 1 threads (one edge and one cell each) for all steps of a run,
-// with its state in registers and LDS, so the run is one launch.
-constexpr int kResidentCells = 255;
+// workgroup of 256 threads, or 512 when a channel has more than 255 cells (one edge and one
+// cell per thread), for all steps of a run, with its state in registers and LDS, so the run
+// is one launch.
+constexpr int kResidentCells = 511;
+constexpr int kResidentSmall = 255;   // channels up to this length use 256-thread workgroups
 
 struct ResidentArgs {
     double *h, *q, *z;           // state, updated in place
@@ -210,8 +212,9 @@ hipError_t launch_dt(const unsigned long long *amax, const ChanInfo *ch, int32_t
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream_t stream);
-// All n_steps of a run of channels of at most kResidentCells cells in one launch.
-hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int grid,
+// All n_steps of a run of channels of at most kResidentCells cells in one launch, with
+// workgroups of `threads` (256 or 512) threads, more than the longest channel has cells.
+hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int threads, int grid,
                            hipStream_t stream);
 // kAmaxSplitMax as compiled into the kernels (the host code checks it against its own).
 int amax_split_of_kernels();

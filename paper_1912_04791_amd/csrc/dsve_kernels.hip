@@ -326,19 +326,19 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     return r;
 }
 
-// Channel-resident run: one workgroup takes one channel of N <= kResidentCells cells (thread i
+// Channel-resident run: one workgroup of NT threads takes one channel of N < NT cells (thread i
 // holds cell i and computes edge i, between cells i-1 and i) through all n steps of the run,
 // with the state in registers, the neighbour states and D^- exchanged through LDS, and the
 // channel's CFL maximum reduced within the workgroup; then the next channel.  Every value is
 // computed as in k_step (same fluctuation, update and speed, same order of operations), so the
 // results are bitwise those of the per-step kernels.
-template <int G, int PREC, int CL>
-__global__ __launch_bounds__(kResidentCells + 1, step_min_waves(PREC, CL) < 3 ? step_min_waves(PREC, CL) : 3)
+template <int G, int PREC, int CL, int NT>
+__global__ __launch_bounds__(NT, step_min_waves(PREC, CL) < 3 ? step_min_waves(PREC, CL) : 3)
 void k_resident(ResidentArgs A)
 {
-    __shared__ double s_st[3][kResidentCells + 1];    // h, q, z of the cells
-    __shared__ double s_dm[3][kResidentCells + 2];    // D^- of the edges
-    __shared__ unsigned long long s_w[(kResidentCells + 64) / 64];
+    __shared__ double s_st[3][NT];        // h, q, z of the cells
+    __shared__ double s_dm[3][NT + 1];    // D^- of the edges
+    __shared__ unsigned long long s_w[NT / 64];
     const int t = threadIdx.x;
     bool bad = false;
     for (int c = blockIdx.x; c < A.n_channels; c += gridDim.x) {
@@ -709,24 +709,32 @@ hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int v, hipStream
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, int NT>
 static hipError_t launch_resident_prec(const ResidentArgs &a, int G, int cl, int grid, hipStream_t s)
 {
-#define DSVE_LAUNCH_RES(GG, CC) hipLaunchKernelGGL((k_resident<GG, PREC, CC>), dim3(grid), \
-                                                   dim3(kResidentCells + 1), 0, s, a)
+#define DSVE_LAUNCH_RES(GG, CC) hipLaunchKernelGGL((k_resident<GG, PREC, CC, NT>), dim3(grid), dim3(NT), 0, s, a)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_RES)
 #undef DSVE_LAUNCH_RES
     return hipGetLastError();
 }
 
-hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int grid,
+template <int NT>
+static hipError_t launch_resident_nt(const ResidentArgs &a, int precision, int G, int cl, int grid,
+                                     hipStream_t stream)
+{
+    if (precision == PREC_FP64) return launch_resident_prec<PREC_FP64, NT>(a, G, cl, grid, stream);
+    if (precision == PREC_MIXED) return launch_resident_prec<PREC_MIXED, NT>(a, G, cl, grid, stream);
+    if (precision == PREC_DOT) return launch_resident_prec<PREC_DOT, NT>(a, G, cl, grid, stream);
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, int threads, int grid,
                            hipStream_t stream)
 {
     if (grid < 1 || a.n_channels < 1 || a.n_steps < 1) return hipErrorInvalidValue;
-    if (precision == PREC_FP64) return launch_resident_prec<PREC_FP64>(a, G, cl, grid, stream);
-    if (precision == PREC_MIXED) return launch_resident_prec<PREC_MIXED>(a, G, cl, grid, stream);
-    if (precision == PREC_DOT) return launch_resident_prec<PREC_DOT>(a, G, cl, grid, stream);
-    return hipErrorNotSupported;
+    if (threads == 256) return launch_resident_nt<256>(a, precision, G, cl, grid, stream);
+    if (threads == 512) return launch_resident_nt<512>(a, precision, G, cl, grid, stream);
+    return hipErrorInvalidValue;
 }
 
 int amax_split_of_kernels() { return kAmaxSplitMax; }

@@ -328,7 +328,7 @@ class Context:
         return v.value
 
     def set_resident(self, mode: int):
-        """0: channel-resident runs when every channel has at most 255 cells; 1: never."""
+        """0: channel-resident runs when every channel has at most 511 cells; 1: never."""
         self._check(lib.dsve_set_resident(self._h, mode), "dsve_set_resident")
 
     def get_resident(self) -> bool:

@@ -1,5 +1,5 @@
-"""Channel-resident runs on the MI355X: every channel of at most 255 cells held by one
-workgroup for all steps of a run.  The results must be bitwise those of the per-step kernels
+"""Channel-resident runs on the MI355X: every channel of at most 511 cells held by one
+workgroup (256 threads, or 512 past 255 cells) for all steps of a run.  The results must be bitwise those of the per-step kernels
 (same arithmetic in the same order), and match the oracle to the FP64 / mixed bars.
 """
 import numpy as np
@@ -45,6 +45,12 @@ def short(name):
         return inputs.make_c1(n_cells=255, steps=37)
     if name == "c1_1":
         return inputs.make_c1(n_cells=1, steps=9)
+    if name == "c1_256":
+        return inputs.make_c1(n_cells=256, steps=41)
+    if name == "c1_511":
+        return inputs.make_c1(n_cells=511, steps=23)
+    if name == "ragged_511":
+        return inputs.make_c4(n_channels=30, len_lo=200, len_hi=511, steps=19)
     if name == "periodic":
         return inputs.make_c2(n_cells=255, steps=61)
     if name == "ragged":
@@ -60,7 +66,8 @@ def short(name):
     raise KeyError(name)
 
 
-CASES = ["c1", "c1_255", "c1_1", "periodic", "ragged", "soni", "bellal_mpm", "bellal_vanrijn", "berthon"]
+CASES = ["c1", "c1_255", "c1_1", "c1_256", "c1_511", "ragged_511", "periodic", "ragged", "soni", "bellal_mpm",
+         "bellal_vanrijn", "berthon"]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -73,7 +80,7 @@ def test_resident_equals_per_step_kernels_bitwise(torch_dev, dsve, name, precisi
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("name", ["c1", "ragged", "soni", "berthon"])
+@pytest.mark.parametrize("name", ["c1", "ragged", "ragged_511", "soni", "berthon"])
 def test_resident_matches_oracle(torch_dev, dsve, name):
     wl = short(name)
     ref = oracle_run(wl)
@@ -118,12 +125,15 @@ def test_resident_eligibility(torch_dev, dsve):
         ctx.set_resident(2)
     ctx.clear_error()
     ctx.close()
-    ctx = dsve.Context.from_workload(inputs.make_c1(n_cells=256))
+    ctx = dsve.Context.from_workload(inputs.make_c1(n_cells=511))
+    assert ctx.get_resident()
+    ctx.close()
+    ctx = dsve.Context.from_workload(inputs.make_c1(n_cells=512))
     assert not ctx.get_resident()
     ctx.close()
-    wl = inputs.make_c4(n_channels=8, len_lo=10, len_hi=300, steps=1)
+    wl = inputs.make_c4(n_channels=8, len_lo=10, len_hi=700, steps=1)
     ctx = dsve.Context.from_workload(wl)
-    assert ctx.get_resident() == bool(wl.lengths().max() <= 255)
+    assert ctx.get_resident() == bool(wl.lengths().max() <= 511)
     ctx.close()
 
 
