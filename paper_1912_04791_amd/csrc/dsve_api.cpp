@@ -1,11 +1,13 @@
 // dsve_api.cpp -- host side of libdsve.so: the C ABI declared in include/dsve.h.
 //
 // A context owns: per-channel records and edge offsets on the device, the tile table of the
-// fused step kernel, one ping-pong copy of the state and clocks, three rotating CFL-maximum slots per
-// channel, a flag word for deferred device errors, and a cached HIP graph of `graph_steps`
-// fused steps.  A run of n steps is: clear slots -> CFL max of W^0 into slot 0 -> graph
-// replays (each node is one step kernel; slot and ping-pong phase repeat every 6 steps, so
-// graph_steps is a multiple of 6) -> leftover steps launched directly -> copy back when n is odd.
+// fused step kernel, one ping-pong copy of the state and clocks, three rotating CFL-maximum slots
+// (each with up to 4 sub-slots per channel), a flag word for deferred device errors, and a cached
+// HIP graph of `graph_steps` fused steps.  A run of n steps is: clear slots -> CFL max of W^0
+// into slot 0 -> graph replays (each node is one step kernel; slot and ping-pong phase repeat
+// every 6 steps, so graph_steps is a multiple of 6) -> leftover steps launched directly -> copy
+// back when n is odd.  When every channel has at most kResidentCells cells the run is instead
+// one channel-resident launch for all n steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -766,7 +768,8 @@ static bool cache_lookup(const char *path, const std::string &key, int &tile, in
     if (!f) return false;
     std::string line;
     while (std::getline(f, line)) {
-        // one entry per line: {"key": "<key>", "tile": T, "blocks_per_cu": B}
+        // one entry per line: {"key": "<key>", "tile": T, "blocks_per_cu": B, "cfl_split": S,
+        // "resident_mode": M, ...} (older entries without S or M read as 0)
         const std::string pat = "\"key\": \"" + key + "\"";
         if (line.find(pat) == std::string::npos) continue;
         const size_t pt = line.find("\"tile\": ");
