@@ -84,9 +84,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per step-kernel launch from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def _profile_entry(workload: str, precision: str):
+    """Committed counter summary of the step kernel, if it was taken on the current kernel
+    code (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -96,7 +96,31 @@ def measured_traffic(workload: str, precision: str):
     ent = d.get(f"{workload}:{precision}")
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per step-kernel launch from the committed counter summary (or None)."""
+    ent = _profile_entry(workload, precision)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+# VALU issue: every wave64 VALU instruction holds a 16-lane SIMD for 4 cycles (FP64 or FP32,
+# packed FP32 being off); 256 compute units x 4 SIMDs at 2.4 GHz
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+CYCLES_PER_WAVE_INST = 4
+
+
+def valu_issue(workload: str, precision: str, edges: int, ms_per_step: float):
+    """Share of the chip's VALU issue slots the step kernel's instruction stream fills at the
+    measured step time, from the committed VALU counter (instructions per edge update), or None."""
+    ent = _profile_entry(workload, precision)
+    if ent is None or "valu_insts_per_edge" not in ent:
+        return None
+    per_edge = ent["valu_insts_per_edge"]
+    busy_s = per_edge * edges / 64.0 * CYCLES_PER_WAVE_INST / SIMDS / CLOCK_HZ
+    return {"insts_per_edge": per_edge, "frac": busy_s / (ms_per_step * 1e-3)}
 
 
 def make_workload(name: str):
@@ -310,7 +334,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved_tflops / peak,
                      "traffic": traffic,
                      "kernel": f"k_step<{wl.n_gauss}, {'FP64' if main_prec == 'fp64' else 'MIXED'}, {form}>",
-                     "ops_per_edge_update": ops},
+                     "ops_per_edge_update": ops,
+                     "valu_issue": valu_issue(wl.name, main_prec, edges, main["ms_per_step"])},
     }
     if wl.law != 0:
         out["roofline"]["note"] = ("ops count the scheme only; the closure's powers and roots "
@@ -325,7 +350,8 @@ def main():
                                 "graph_steps": r["launch"][2], "cfl_split": r["launch"][3]},
                      "roofline": {"bound": "alu", "achieved": achieved_p, "peak": peak_p,
                                   "unit": "TFLOP/s", "frac": achieved_p / peak_p,
-                                  "traffic": measured_traffic(wl.name, prec)}}
+                                  "traffic": measured_traffic(wl.name, prec),
+                                  "valu_issue": valu_issue(wl.name, prec, edges, r["ms_per_step"])}}
 
     if args.dot_steps > 0:
         # the paper's own baseline: the same scheme with the numerical eigen-decomposition

@@ -29,3 +29,17 @@ def test_traffic_is_used_only_for_the_current_code(tmp_path, monkeypatch):
     assert bench.measured_traffic("c2", "fp64") == 1.0e6
     assert bench.measured_traffic("c2", "mixed") is None
     assert bench.measured_traffic("c3", "fp64") is None
+
+
+def test_valu_issue_share_from_the_counter_summary(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    ent = {"kernel_hash": "h", "valu_insts_per_edge": 640.0}
+    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ent}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h")
+    # 640 instructions per edge, 2^20 edges: 2^14 waves x 640 x 4 cycles / 1024 SIMDs / 2.4 GHz
+    busy = 2 ** 14 * 640 * 4 / 1024 / 2.4e9
+    v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
+    assert v["insts_per_edge"] == 640.0 and abs(v["frac"] - 0.5) < 1e-12
+    assert bench.valu_issue("c3", "fp64", 2 ** 20, 1.0) is None
