@@ -147,10 +147,16 @@ def test_full_size_c4_fp64_sampled_channels(torch_dev, dsve):
 
 
 def test_full_size_c5_mixed_sampled_channels(torch_dev, dsve):
-    # all 65536 channels (1.5e8 cells) for 300 of the 5000 steps; 32 channels checked
+    # all 65536 channels (1.5e8 cells) for the full 5000 steps; 32 channels checked
     wl = inputs.make_c5()
-    wl.steps = 300
+    assert wl.steps == 5000
     _sampled_channels_check(dsve, wl, "mixed", 1e-5, every=2048)
+
+
+def test_full_size_c5_fp64_sampled_channels(torch_dev, dsve):
+    # the same run in FP64; 16 channels checked
+    wl = inputs.make_c5()
+    _sampled_channels_check(dsve, wl, "fp64", 1e-12, every=4096)
 
 
 def test_wide_index_path_sampled_channels(torch_dev, dsve):
