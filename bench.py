@@ -71,12 +71,14 @@ def _code_only(text: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the code (comments and whitespace removed) of the kernel sources and the
-    build flags: a counter summary stays valid across edits that change no code."""
+    """Hash of the code (comments and whitespace removed) of the device sources (`.hip` and
+    the headers they include) and the build flags: a counter summary stays valid across edits
+    that change no kernel code.  The host `.cpp` is left out: it chooses launches, which each
+    summary records, and compiles no device code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_04791_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".hpp")):
             with open(os.path.join(csrc, name), encoding="utf-8") as f:
                 h.update(_code_only(f.read()).encode())
     with open(os.path.join(ROOT, "paper_1912_04791_amd", "build.py"), encoding="utf-8") as f:

@@ -272,10 +272,15 @@ dsve_status dsve_get_resident(const dsve_ctx *ctx, int *active);
  * over tiles of 64..256 threads and 0..128 workgroups per compute unit, then the three
  * fastest with 1 and with 4 CFL sub-slots -- the caller's arrays are read, never written
  * -- and keep the fastest in the context.  If cache_path is not NULL, a JSON cache keyed
- * by device, precision, law and problem shape is read first and updated after tuning.
+ * by device, precision, law, kernel closure and problem shape is read first (a hit sets the
+ * launch and returns at once) and updated after tuning.
  * When the context can run channel-resident (and that is not turned off), a resident run
  * is timed too: it stays on if it is the fastest, else it is turned off (mode 1) for the
- * context.  Waits for completion. */
+ * context.  Waits for completion.  Before the trials it waits for the work already
+ * enqueued and returns that work's deferred error, as dsve_sync would; the trials' own
+ * device error flags and CFL maxima are discarded, so a later dsve_sync reports only runs
+ * made after tuning.  If a trial fails, the error is sticky and the context keeps the
+ * launch it had before the call. */
 dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const double *q, const double *z,
                           int trial_steps, const char *cache_path);
 

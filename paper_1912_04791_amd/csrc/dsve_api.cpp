@@ -753,7 +753,8 @@ static std::string tune_key(const dsve_ctx *ctx)
         ++hist[b];
     }
     std::ostringstream os;
-    os << ctx->arch << "|cu" << ctx->cus << "|p" << ctx->precision << "|law" << ctx->law << "|G" << ctx->G << "|C"
+    os << ctx->arch << "|cu" << ctx->cus << "|p" << ctx->precision << "|law" << ctx->law << "|cl" << ctx->cl
+       << "|G" << ctx->G << "|C"
        << ctx->n_channels << "|N" << ctx->n_cells << "|h";
     for (int b = 0; b < 40; ++b)
         if (hist[b]) os << b << ":" << hist[b] << ",";
@@ -823,15 +824,35 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
         return st != DSVE_OK ? st : dsve_set_resident(ctx, resident);
     }
 
+    // the work already enqueued finishes first and its deferred errors are reported here, so
+    // that the trial runs below, whose flags and CFL slots are discarded, hide none of them
+    dsve_status pending = dsve_sync(ctx);
+    if (pending != DSVE_OK) return pending;
+
+    // scratch copy of the state and the timing events, released on every return
+    struct Scratch {
+        hipStream_t stream = nullptr;
+        double *p[4] = {nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~Scratch()
+        {
+            (void)hipStreamSynchronize(stream);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            for (double *x : p)
+                if (x) (void)hipFree(x);
+        }
+    } scr;
+    scr.stream = ctx->stream;
     const size_t bytes = sizeof(double) * ctx->n_cells;
-    double *sh = nullptr, *sq = nullptr, *sz = nullptr, *st_ = nullptr;
-    HIP_TRY(ctx, hipMalloc(&sh, bytes));
-    HIP_TRY(ctx, hipMalloc(&sq, bytes));
-    HIP_TRY(ctx, hipMalloc(&sz, bytes));
-    HIP_TRY(ctx, hipMalloc(&st_, sizeof(double) * ctx->n_channels));
-    hipEvent_t e0, e1;
-    HIP_TRY(ctx, hipEventCreate(&e0));
-    HIP_TRY(ctx, hipEventCreate(&e1));
+    HIP_TRY(ctx, hipMalloc(&scr.p[0], bytes));
+    HIP_TRY(ctx, hipMalloc(&scr.p[1], bytes));
+    HIP_TRY(ctx, hipMalloc(&scr.p[2], bytes));
+    HIP_TRY(ctx, hipMalloc(&scr.p[3], sizeof(double) * ctx->n_channels));
+    HIP_TRY(ctx, hipEventCreate(&scr.ev[0]));
+    HIP_TRY(ctx, hipEventCreate(&scr.ev[1]));
+    double *sh = scr.p[0], *sq = scr.p[1], *sz = scr.p[2], *st_ = scr.p[3];
+    hipEvent_t e0 = scr.ev[0], e1 = scr.ev[1];
     // tile sizes: whole waves; 192 (191 cells per tile) gives the power-of-two channel lengths
     // a tile count that divides more evenly over the persistent grid than 255 or 127
     const int tiles[] = {64, 128, 192, 256};
@@ -842,8 +863,10 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
     // Candidates run the way a run will: replays of a captured graph when the context uses
     // graphs (a warm-up run captures it, the timed run replays it; 12-step graphs keep the
     // trials short), direct launches if not.
+    const int save_tile = ctx->tile, save_bpc = ctx->blocks_per_cu;
     const int save_graph = ctx->graph_steps;
     const int save_split = ctx->cfl_split;
+    const int save_mode = ctx->resident_mode;
     const int tg = save_graph > 0 ? std::min(save_graph, 12) : 0;
     const int warm = tg > 0 ? tg : 2;
     const int timed = tg > 0 ? std::max(tg, (trial_steps + tg - 1) / tg * tg) : trial_steps;
@@ -900,14 +923,18 @@ extern "C" dsve_status dsve_autotune(dsve_ctx *ctx, const double *h, const doubl
         }
     }
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(sh);
-    (void)hipFree(sq);
-    (void)hipFree(sz);
-    (void)hipFree(st_);
+    // the trials' device error flags and CFL maxima describe scratch runs, not the caller's
+    // state: clear them (the flags were clear before the trials, as dsve_sync checked)
+    HIP_TRY(ctx, launch_fill_u32(ctx->d_flags, 4, 0u, ctx->stream));
+    ctx->last_amax_slot = -1;
     if (status != DSVE_OK) {
-        if (try_resident) ctx->resident_mode = 0;
+        // back to the launch the context had before tuning (the error stays sticky)
+        ctx->tile = save_tile;
+        ctx->blocks_per_cu = save_bpc;
+        ctx->graph_steps = save_graph;
+        ctx->cfl_split = save_split;
+        ctx->resident_mode = save_mode;
+        free_graph(ctx);
         return status;
     }
     Cand best{1e30f, ctx->tile, ctx->blocks_per_cu, save_split};

@@ -72,6 +72,43 @@ def test_autotune_keeps_results_and_writes_cache(torch_dev, dsve, tmp_path):
         c.close()
 
 
+def test_autotune_reports_pending_error_first(torch_dev, dsve):
+    # a run on a state with a negative depth, enqueued and not yet synchronised: the
+    # autotuner waits for it and returns its deferred error before any trial
+    wl = inputs.make_c1(n_cells=300, steps=5)
+    wl.h[17] = -0.5
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    launch = tuple(ctx.get_launch())
+    ctx.adot_step(h, q, z, 5, t)
+    with pytest.raises(dsve.DsveError) as err:
+        ctx.autotune(h, q, z, trial_steps=4)
+    assert err.value.status == dsve.E_NONFINITE
+    assert tuple(ctx.get_launch()) == launch
+    ctx.close()
+
+
+@pytest.mark.parametrize("resident", [0, 1])
+def test_autotune_trials_leave_no_error_behind(torch_dev, dsve, resident):
+    # tuned on a state that is not finite: the trial runs meet it, but only the caller's own
+    # runs after tuning are reported
+    wl = inputs.make_c1(n_cells=300, steps=5)
+    ctx = dsve.Context.from_workload(wl)
+    ctx.set_resident(resident)
+    good = dsve.upload(wl)
+    wl.h[17] = -0.5
+    bad = dsve.upload(wl)
+    ctx.autotune(*bad[:3], trial_steps=4)
+    assert ctx.sync_status() == dsve.OK
+    ctx.adot_step(*good[:3], 5, good[3])
+    ctx.sync()
+    ref = oracle_run(inputs.make_c1(n_cells=300, steps=5))
+    assert max_rel_l1(to_np(*good), ref) <= 1e-12
+    ctx.adot_step(*bad[:3], 5, bad[3])
+    assert ctx.sync_status() == dsve.E_NONFINITE
+    ctx.close()
+
+
 def test_graph_recaptured_for_new_buffers(torch_dev, dsve):
     wl = inputs.make_c2(n_cells=40_000, steps=120)
     ctx = dsve.Context.from_workload(wl)
