@@ -132,13 +132,21 @@ class DsveError(RuntimeError):
         self.status = status
 
 
-def _ptr(t) -> int:
-    """Device pointer of a contiguous float64 CUDA tensor."""
+def _ptr(t, numel: int | None = None, at_least: int | None = None, device: int | None = None) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor, after checking its element count
+    (exactly ``numel``, or at least ``at_least``) and its device: the library takes raw
+    pointers and trusts the sizes it was given."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch.Tensor")
     if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise ValueError("expected a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    if at_least is not None and t.numel() < at_least:
+        raise ValueError(f"expected at least {at_least} elements, got {t.numel()}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"tensor on cuda:{t.device.index}, context on cuda:{device}")
     return t.data_ptr()
 
 
@@ -210,10 +218,16 @@ class Context:
     """One libdsve context (single channel or batched).  Methods map 1:1 to entry points."""
 
     def __init__(self, handle, n_cells: int, n_channels: int, batched: bool):
+        import torch
         self._h = handle
         self.n_cells = n_cells
         self.n_channels = n_channels
         self.batched = batched
+        self.device = torch.cuda.current_device()   # the device the library bound it to
+
+    def _state(self, h, q, z):
+        n, d = self.n_cells, self.device
+        return _ptr(h, n, device=d), _ptr(q, n, device=d), _ptr(z, n, device=d)
 
     # -- construction -----------------------------------------------------
     @classmethod
@@ -280,21 +294,29 @@ class Context:
 
     # -- entry points -----------------------------------------------------
     def dot_edge_fluct(self, hL, qL, zL, hR, qR, zR, Dm, Dp):
-        n = hL.numel()
-        self._check(lib.dot_edge_fluct(self._h, _ptr(hL), _ptr(qL), _ptr(zL), _ptr(hR), _ptr(qR),
-                                       _ptr(zR), n, _ptr(Dm), _ptr(Dp)), "dot_edge_fluct")
+        """n edges: six states of n elements each; Dm, Dp hold [3][n]."""
+        n, d = hL.numel(), self.device
+        ins = [_ptr(x, n, device=d) for x in (hL, qL, zL, hR, qR, zR)]
+        self._check(lib.dot_edge_fluct(self._h, *ins, n, _ptr(Dm, 3 * n, device=d),
+                                       _ptr(Dp, 3 * n, device=d)), "dot_edge_fluct")
 
     def cell_update(self, Dm, Dp, dt, h, q, z):
-        self._check(lib.cell_update(self._h, _ptr(Dm), _ptr(Dp), _ptr(dt), _ptr(h), _ptr(q),
-                                    _ptr(z)), "cell_update")
+        """Dm, Dp hold [3][N+1] edge fluctuations of an N-cell channel; dt one value."""
+        e, d = 3 * (self.n_cells + 1), self.device
+        self._check(lib.cell_update(self._h, _ptr(Dm, e, device=d), _ptr(Dp, e, device=d),
+                                    _ptr(dt, at_least=1, device=d), *self._state(h, q, z)),
+                    "cell_update")
 
     def cfl_reduce(self, h, q, z, amax, dt):
-        self._check(lib.cfl_reduce(self._h, _ptr(h), _ptr(q), _ptr(z), _ptr(amax), _ptr(dt)),
-                    "cfl_reduce")
+        d = self.device
+        self._check(lib.cfl_reduce(self._h, *self._state(h, q, z), _ptr(amax, at_least=1, device=d),
+                                   _ptr(dt, at_least=1, device=d)), "cfl_reduce")
 
     def adot_step(self, h, q, z, n_steps: int, t):
+        """n_steps steps in place; t holds one clock per channel."""
         fn = lib.adot_step_batched if self.batched else lib.adot_step
-        self._check(fn(self._h, _ptr(h), _ptr(q), _ptr(z), int(n_steps), _ptr(t)), "adot_step")
+        self._check(fn(self._h, *self._state(h, q, z), int(n_steps),
+                       _ptr(t, self.n_channels, device=self.device)), "adot_step")
 
     def sync(self):
         self._check(lib.dsve_sync(self._h), "dsve_sync")
@@ -338,7 +360,7 @@ class Context:
 
     def autotune(self, h, q, z, trial_steps: int = 10, cache_path: str | None = None):
         cp = cache_path.encode() if cache_path else None
-        self._check(lib.dsve_autotune(self._h, _ptr(h), _ptr(q), _ptr(z), trial_steps, cp),
+        self._check(lib.dsve_autotune(self._h, *self._state(h, q, z), trial_steps, cp),
                     "dsve_autotune")
 
     def device_cus(self) -> int:

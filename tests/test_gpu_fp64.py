@@ -295,3 +295,34 @@ def test_bad_launch_arguments(torch_dev, dsve):
             ctx.set_cfl_split(bad)
         ctx.clear_error()
     ctx.close()
+
+
+def test_binding_refuses_wrong_sizes_before_launch(torch_dev, dsve):
+    torch = torch_dev
+    wl = inputs.make_c1(n_cells=300, steps=5)
+    ctx = dsve.Context.from_workload(wl)
+    h, q, z, t = dsve.upload(wl)
+    short = h[:-1].contiguous()
+    f64 = dict(dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.adot_step(short, q, z, 5, t)
+    with pytest.raises(ValueError):
+        ctx.adot_step(h, q, z, 5, torch.zeros(0, **f64))
+    with pytest.raises(ValueError):
+        ctx.autotune(h, short, z)
+    with pytest.raises(ValueError):
+        ctx.cfl_reduce(h, q, z, torch.zeros(0, **f64), torch.zeros(1, **f64))
+    E = wl.n_cells + 1
+    with pytest.raises(ValueError):
+        ctx.cell_update(torch.zeros(3, E - 1, **f64), torch.zeros(3, E, **f64),
+                        torch.zeros(1, **f64), h, q, z)
+    with pytest.raises(ValueError):
+        ctx.dot_edge_fluct(*[torch.ones(8, **f64)] * 5, torch.ones(7, **f64),
+                           torch.zeros(3, 8, **f64), torch.zeros(3, 8, **f64))
+    with pytest.raises(ValueError):
+        ctx.dot_edge_fluct(*[torch.ones(8, **f64)] * 6, torch.zeros(3, 7, **f64),
+                           torch.zeros(3, 8, **f64))
+    # nothing was enqueued; the context still runs
+    ctx.adot_step(h, q, z, 5, t)
+    ctx.sync()
+    ctx.close()
