@@ -91,6 +91,12 @@ _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _ctxp = ctypes.c_void_p
 
+# PyTorch brings its own HIP runtime.  It is loaded first so that the library binds to that
+# same runtime: loaded before it, the library would pull in the system runtime beside torch's,
+# and the streams and memory that torch hands over would be unknown to the runtime the library
+# calls (dsve_init then fails on the stream).
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 lib.dsve_abi_version.restype = ctypes.c_int
 lib.dsve_init.argtypes = [ctypes.POINTER(_ctxp), ctypes.POINTER(Params), _i64, _vp]

@@ -31,6 +31,8 @@ def test_header_declares_the_boundary():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdsve.so not built")
 def test_library_exports_every_declared_symbol():
+    # torch's HIP runtime first, so that a GPU test later in this process finds only that one
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
@@ -110,3 +112,17 @@ def test_struct_mirrors_match_the_header(tmp_path):
         assert int(out[cname]) == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdsve.so not built")
+def test_binding_shares_torchs_hip_runtime_whatever_the_import_order():
+    # imported before torch, the binding must still leave one HIP runtime in the process:
+    # a second one would not know torch's streams and memory
+    import subprocess
+    import sys
+    code = ("import paper_1912_04791_amd.dsve, torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
