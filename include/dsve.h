@@ -33,6 +33,11 @@
  *     Errors are sticky per context until dsve_clear_error().
  *   - One context per stream; contexts share no state.  Calls that overlap on
  *     the same context from several host threads are not supported.
+ *   - The library calls the HIP runtime it finds loaded (libamdhip64.so.7).  A
+ *     caller whose streams and memory come from a HIP runtime of its own (one
+ *     bundled with a framework) loads that runtime before this library, so that
+ *     the process holds one runtime; with two, the caller's streams and pointers
+ *     are unknown to the library's and init fails with DSVE_E_HIP.
  */
 #ifndef DSVE_H
 #define DSVE_H
