@@ -74,6 +74,30 @@ def test_pairwise_fluct_matches_oracle(torch_dev, dsve, G):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 257])
+def test_pairwise_fluct_small_and_ragged_edge_counts(torch_dev, dsve, n, precision):
+    # no edges (nothing launched), one edge, and counts just off whole waves and workgroups
+    torch = torch_dev
+    WL, WR = inputs.make_random_edges(max(n, 1), seed=300 + n)
+    WL, WR = tuple(a[:n] for a in WL), tuple(a[:n] for a in WR)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.02, dx=1.0, precision=precision)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (*WL, *WR)]
+    # padded outputs: what lies past [3][n] must stay untouched
+    Dm = torch.full((3 * n + 64,), 7.0, dtype=torch.float64, device="cuda")
+    Dp = torch.full_like(Dm, 7.0)
+    ctx.dot_edge_fluct(*dev, Dm[:3 * n], Dp[:3 * n])
+    ctx.sync()
+    assert torch.all(Dm[3 * n:] == 7.0) and torch.all(Dp[3 * n:] == 7.0)
+    if n:
+        rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, 0.02)
+        tol = TOL if precision == "fp64" else 1e-5
+        for got, ref in ((Dm[:3 * n], rm), (Dp[:3 * n], rp)):
+            got = got.cpu().numpy().reshape(3, n)
+            assert np.abs(got - ref).sum() <= tol * np.abs(ref).sum()
+    ctx.close()
+
+
 def test_cfl_reduce_matches_oracle(torch_dev, dsve):
     torch = torch_dev
     wl = inputs.make_c3(n_cells=300_001)
