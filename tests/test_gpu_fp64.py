@@ -350,3 +350,30 @@ def test_binding_refuses_wrong_sizes_before_launch(torch_dev, dsve):
     ctx.adot_step(h, q, z, 5, t)
     ctx.sync()
     ctx.close()
+
+
+@pytest.mark.parametrize("resident", [0, 1])
+def test_runs_write_only_the_callers_arrays(torch_dev, dsve, resident):
+    # ragged batched channels, an odd step count (ends with the copy back); the caller's
+    # arrays are views into padded buffers whose padding must stay untouched
+    torch = torch_dev
+    wl = inputs.make_c4(n_channels=5, len_lo=100, len_hi=400, steps=7)
+    ctx = dsve.Context.from_workload(wl)
+    ctx.set_resident(resident)
+    assert ctx.get_resident() == (resident == 0)
+    pad = 256
+    bufs = []
+    for a in (wl.h, wl.q, wl.z, np.zeros(wl.n_channels)):
+        b = torch.full((a.size + 2 * pad,), 7.0, dtype=torch.float64, device="cuda")
+        b[pad:pad + a.size] = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        bufs.append(b)
+    h, q, z, t = (b[pad:-pad] for b in bufs)
+    ctx.adot_step(h, q, z, wl.steps, t)
+    ctx.sync()
+    for b in bufs:
+        assert torch.all(b[:pad] == 7.0) and torch.all(b[-pad:] == 7.0)
+    got = tuple(x.cpu().numpy() for x in (h, q, z, t))
+    ref = oracle_run(wl)
+    assert per_channel_rel_l1(got, ref, wl.offsets).max() <= TOL
+    np.testing.assert_allclose(got[3], ref[3], rtol=1e-13)
+    ctx.close()
