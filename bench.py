@@ -274,6 +274,8 @@ def main():
     torch.cuda.set_device(0)
 
     if args.calib_copy_mib > 0:
+        # a plain device copy of known size, the first copy of the run (counter summaries
+        # scale FETCH_SIZE / WRITE_SIZE by what they read for it)
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -11,9 +11,9 @@ calibration, hardware FLOP counts), plus an entry in ``profiles/traffic.json`` k
 workload and precision and stamped with the hash of the kernel sources it was taken on.
 
 The calibration: bench.py --calib-copy-mib M first copies M MiB device-to-device (one
-``__amd_rocclr_copyBuffer`` dispatch reading and writing exactly M MiB); the ratio of the
-known bytes to what FETCH_SIZE / WRITE_SIZE report for that dispatch scales the step
-kernel's readings.
+``__amd_rocclr_copyBuffer`` dispatch reading and writing exactly M MiB, the run's first copy);
+the ratio of the known bytes to what FETCH_SIZE / WRITE_SIZE report for that dispatch scales
+the step kernel's readings.
 """
 from __future__ import annotations
 
@@ -44,7 +44,10 @@ def kernel_stats(trace_dir: str, kernel: str):
 
 
 def counters(pmc_dir: str, kernel: str):
-    """Per-counter list of per-dispatch values for the kernel, and the copy dispatches."""
+    """Per-counter list of per-dispatch values for the kernel, and per counter the value of the
+    calibration copy: the first copy dispatch of the run, since bench.py issues it before any
+    other copy (later copies, such as the state copied back after an odd step count, can be
+    larger than it)."""
     path = _one(os.path.join(pmc_dir, "**", "*counter_collection.csv"))
     out, copies = {}, {}
     for r in csv.DictReader(open(path)):
@@ -53,8 +56,9 @@ def counters(pmc_dir: str, kernel: str):
         if kernel in name:
             out.setdefault(r["Counter_Name"], []).append(v)
         elif "copyBuffer" in name:
-            copies.setdefault(r["Counter_Name"], []).append(v)
-    return out, copies
+            copies.setdefault(r["Counter_Name"], []).append((int(r["Dispatch_Id"]), v))
+    first = {k: min(vs)[1] for k, vs in copies.items()}
+    return out, first
 
 
 def main():
@@ -91,8 +95,8 @@ def main():
     if args.fetch and args.write:
         f, fc = counters(args.fetch, args.kernel)
         w, wc = counters(args.write, args.kernel)
-        f_copy = max(fc["FETCH_SIZE"])
-        w_copy = max(wc["WRITE_SIZE"])
+        f_copy = fc["FETCH_SIZE"]
+        w_copy = wc["WRITE_SIZE"]
         sf, sw = known / f_copy, known / w_copy
         fk = statistics.median(f["FETCH_SIZE"])
         wk = statistics.median(w["WRITE_SIZE"])

@@ -43,3 +43,23 @@ def test_valu_issue_share_from_the_counter_summary(tmp_path, monkeypatch):
     v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
     assert v["insts_per_edge"] == 640.0 and abs(v["frac"] - 0.5) < 1e-12
     assert bench.valu_issue("c3", "fp64", 2 ** 20, 1.0) is None
+
+
+def test_profile_calibration_is_the_first_copy(tmp_path):
+    # a run whose later copies (the state copied back after an odd step count) are larger
+    # than the calibration copy: the scale comes from the first copy dispatch
+    from paper_1912_04791_amd import profsum
+    hdr = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id",'
+           '"Grid_Size","Kernel_Id","Kernel_Name","Workgroup_Size","LDS_Block_Size",'
+           '"Scratch_Size","VGPR_Count","Accum_VGPR_Count","SGPR_Count","Counter_Name",'
+           '"Counter_Value","Start_Timestamp","End_Timestamp"')
+    def row(d, name, v):
+        return f'{d},{d},"Agent 1",1,1,1,131072,1,"{name}",512,0,0,4,0,32,"FETCH_SIZE",{v},0,1'
+    lines = [hdr, row(1, "fill_kernel", 17.0), row(2, "__amd_rocclr_copyBuffer", 131092.0),
+             row(7, "dsve::k_step<3, 0, 0, false>", 500.0),
+             row(9, "__amd_rocclr_copyBuffer", 590570.0),
+             row(8, "dsve::k_step<3, 0, 0, false>", 520.0)]
+    (tmp_path / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
+    out, first = profsum.counters(str(tmp_path), "k_step<3, 0, 0, false>")
+    assert first["FETCH_SIZE"] == 131092.0
+    assert sorted(out["FETCH_SIZE"]) == [500.0, 520.0]
