@@ -189,22 +189,25 @@ __device__ __forceinline__ T ipow15(T a, int n)
 // error: about 4e-7 -> 7e-13 -> the rounding of y^9, a few ulp)
 __device__ __forceinline__ double pow_1p1(double a);
 __device__ __forceinline__ float pow_1p1(float a) { return m_pow(a, 1.1f); }
-// cube root of a > 0: FP32 estimate, then one Halley step y (y^3 + 2a) / (2y^3 + a) in FP64
-// (cubic convergence: about 2^-23 -> 2^-69 relative)
-__device__ __forceinline__ double cbrt_h(double a)
+// a^(-1/3), a > 0: FP32 estimate 2^(-log2(a)/3) from the hardware base-2 logarithm and
+// exponential, then two Newton steps for y^-3 = a, y <- y (4 - a y^3) / 3, in FP64 (each takes a
+// relative error e to about 2 e^2: 1e-6 -> 2e-12 -> the rounding of the last step); no division
+__device__ __forceinline__ double rcbrt_h(double a)
 {
-    const double y = (double)cbrtf((float)a);
-    const double y3 = y * y * y;
-    return y * fma(2.0, a, y3) * rcp_h(fma(2.0, y3, a));
+    double y = (double)__builtin_amdgcn_exp2f(-(1.0f / 3.0f) * __builtin_amdgcn_logf((float)a));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = (y * (1.0 / 3.0)) * fma(-a, y * y * y, 4.0);
+    return y;
 }
-__device__ __forceinline__ double m_cbrt(double a) { return cbrt_h(a); }
-__device__ __forceinline__ float m_cbrt(float a) { return cbrtf(a); }
+__device__ __forceinline__ double m_rcbrt(double a) { return rcbrt_h(a); }
+__device__ __forceinline__ float m_rcbrt(float a)
+{
+    return __builtin_amdgcn_exp2f(-(1.0f / 3.0f) * __builtin_amdgcn_logf(a));
+}
 __device__ __forceinline__ double m_sqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float m_sqrt(float a) { return sqrtf(a); }
 __device__ __forceinline__ double m_abs(double a) { return fabs(a); }
 __device__ __forceinline__ float m_abs(float a) { return fabsf(a); }
-__device__ __forceinline__ double m_rcp(double a) { return rcp_h(a); }
-__device__ __forceinline__ float m_rcp(float a) { return 1.0f / a; }
 __device__ __forceinline__ double pow_1p1(double a)
 {
     double y = (double)__builtin_amdgcn_exp2f(0.1f * __builtin_amdgcn_logf((float)fmax(a, 1e-30)));
@@ -234,12 +237,16 @@ __device__ __forceinline__ T law_b(const Closure &K, T h, T q, T invh)
     } else if constexpr (CL == CL_POWER_INT) {
         return au > T(0) ? lp0 * ipow15(au, K.ipow) * invh : T(0);
     } else if constexpr (CL == CL_MPM) {
-        const T th = lp0 * (u * u) * m_rcp(m_cbrt(h));              // Shields stress
-        return th > T(0.047) ? lp1 * m_sqrt(th - T(0.047)) * th * m_rcp(m_abs(q)) : T(0);
+        // b = lp1 sqrt(th - 0.047) th / |q| with the Shields stress th = lp0 u^2 h^(-1/3); since
+        // |q| = h |u|, th / |q| = lp0 |u| h^(-1/3) / h, which needs no reciprocal of q
+        const T r = m_rcbrt(h);
+        const T th = lp0 * (u * u) * r;
+        return th > T(0.047) ? lp1 * m_sqrt(th - T(0.047)) * (lp0 * au * r * invh) : T(0);
     } else {
-        const T tp1 = lp0 * (u * u) * m_rcp(m_cbrt(h));             // u_*^2 / u_*cr^2
-        const T tt = tp1 - T(1);
-        return tt > T(0) ? lp1 * pow_1p1(tt) * tp1 * m_rcp(m_abs(q)) : T(0);
+        // b = lp1 T^1.1 (T + 1) / |q| with T + 1 = u_*^2 / u_*cr^2 = lp0 u^2 h^(-1/3), the same way
+        const T r = m_rcbrt(h);
+        const T tt = lp0 * (u * u) * r - T(1);
+        return tt > T(0) ? lp1 * pow_1p1(tt) * (lp0 * au * r * invh) : T(0);
     }
 }
 
@@ -488,10 +495,12 @@ __device__ __forceinline__ double speed_mixed(double h, double q, double g, cons
 }
 
 // Friction source of the momentum equation (Sec. 2): -g h s_f with
-// s_f = q |q| / (K_s^2 h^(10/3)), fric = 1 / K_s^2; evaluated in FP64 at the old cell state.
+// s_f = q |q| / (K_s^2 h^(10/3)), fric = 1 / K_s^2; evaluated in FP64 at the old cell state,
+// h^(-7/3) as the seventh power of h^(-1/3).
 __device__ __forceinline__ double friction_source(double h, double q, double g, double fric)
 {
-    return -g * (q * fabs(q)) * fric * rcp_h(h * h * cbrt_h(h));
+    const double r = rcbrt_h(h), r2 = r * r;
+    return -g * (q * fabs(q)) * fric * ((r2 * r2) * (r2 * r));
 }
 
 }  // namespace dsve

@@ -124,3 +124,40 @@ def test_integer_power_product():
         r = np.where(n & 4, r * u4, r)
         r = np.where(n & 8, r * u8, r)
         np.testing.assert_allclose(r, u ** n, rtol=4 * 2.2e-16 * max(n, 1))
+
+
+def test_reciprocal_cube_root_newton_reaches_fp64():
+    # a^(-1/3): FP32 estimate 2^(-log2(a)/3) (numpy's float32 exp2/log2 here), then two Newton
+    # steps y <- y (4 - a y^3) / 3 in FP64, as the MPM and Van Rijn closures and the friction
+    # source take it; also from estimates degraded to a relative error of 1e-6
+    a = np.concatenate([np.logspace(-6, 4, 20001), np.linspace(0.01, 3.0, 2001)])
+    y0 = np.exp2(np.float32(-1.0 / 3.0) * np.log2(a.astype(np.float32))).astype(np.float64)
+    exact = a ** (-1.0 / 3.0)
+    assert np.max(np.abs(y0 / exact - 1)) < 1e-6
+    for seed in (y0, exact * (1 + 1e-6), exact * (1 - 1e-6)):
+        y = seed
+        for _ in range(2):
+            y = (y * (1.0 / 3.0)) * (4.0 - a * (y * y * y))
+        np.testing.assert_allclose(y, exact, rtol=1e-15)
+        r2 = y * y
+        np.testing.assert_allclose((r2 * r2) * (r2 * y), a ** (-7.0 / 3.0), rtol=1e-14)
+
+
+def test_stress_law_derivatives_without_reciprocal_of_q():
+    # MPM and Van Rijn: th / |q| with th = lp0 u^2 h^(-1/3) equals lp0 |u| h^(-1/3) / h, since
+    # |q| = h |u|; the rewritten b equals the form with the reciprocal of |q|
+    rng = np.random.default_rng(7)
+    h = rng.uniform(0.01, 3.0, 5000)
+    q = rng.uniform(-5.0, 5.0, 5000)
+    lp0, lp1 = 40.0, 0.3
+    u = q / h
+    r = h ** (-1.0 / 3.0)
+    th = lp0 * u * u * r
+    mpm_q = np.where(th > 0.047, lp1 * np.sqrt(np.maximum(th - 0.047, 0)) * th / np.abs(q), 0)
+    mpm_r = np.where(th > 0.047, lp1 * np.sqrt(np.maximum(th - 0.047, 0)) * (lp0 * np.abs(u) * r / h), 0)
+    np.testing.assert_allclose(mpm_r, mpm_q, rtol=1e-14)
+    tt = th - 1.0
+    vr_q = np.where(tt > 0, lp1 * np.maximum(tt, 0) ** 1.1 * th / np.abs(q), 0)
+    vr_r = np.where(tt > 0, lp1 * np.maximum(tt, 0) ** 1.1 * (lp0 * np.abs(u) * r / h), 0)
+    np.testing.assert_allclose(vr_r, vr_q, rtol=1e-14)
+    assert np.count_nonzero(mpm_q) > 1000 and np.count_nonzero(vr_q) > 1000
