@@ -100,16 +100,23 @@ def test_gap_product_identity():
 
 
 def test_tenth_root_newton_reaches_fp64():
-    # a^1.1 = a * a^(1/10): FP32 estimate 2^(log2(a)/10) (emulated here with numpy's float32
-    # exp2/log2), then two Newton steps for y^10 = a in FP64, as the Van Rijn closure takes it
+    # a^1.1 = a^2 y^9 with y = a^(-1/10): FP32 estimate 2^(-log2(a)/10) (emulated here with
+    # numpy's float32 exp2/log2), then two Newton steps y <- y (11 - a y^10) / 10 in FP64, as the
+    # Van Rijn closure takes it; also from estimates degraded to a relative error of 1e-6
     a = np.concatenate([np.logspace(-15, 3, 20001), np.linspace(0.5, 2.0, 2001)])
-    y = np.exp2(np.float32(0.1) * np.log2(a.astype(np.float32))).astype(np.float64)
-    assert np.max(np.abs(y / a ** 0.1 - 1)) < 1e-6
-    for _ in range(2):
-        y9 = (y * y) ** 2
-        y9 = y9 * y9 * y
-        y = 0.9 * y + (0.1 * a) / y9
-    np.testing.assert_allclose(a * y, a ** 1.1, rtol=5e-15)   # a few ulp: the rounding of y^9
+    y0 = np.exp2(np.float32(-0.1) * np.log2(a.astype(np.float32))).astype(np.float64)
+    exact = a ** -0.1
+    assert np.max(np.abs(y0 / exact - 1)) < 1e-6
+    for seed in (y0, exact * (1 + 1e-6), exact * (1 - 1e-6)):
+        y = seed
+        for _ in range(2):
+            y2 = y * y
+            y5 = y2 * y2 * y
+            y = (y * 0.1) * (11.0 - a * (y5 * y5))
+        y4 = (y * y) * (y * y)
+        np.testing.assert_allclose(y, exact, rtol=1e-15)
+        # y^9 carries nine times y's last-bit rounding: about 6e-15 at worst
+        np.testing.assert_allclose((a * a) * (y4 * y4 * y), a ** 1.1, rtol=8e-15)
 
 
 def test_integer_power_product():
