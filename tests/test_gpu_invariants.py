@@ -1,0 +1,93 @@
+"""Properties the scheme has at any size, checked on the HIP path through the C ABI (MI355X):
+still water at rest stays at rest, a fixed bed (A_g = 0) never moves, and over a fixed bed a
+supercritical edge sends nothing upstream (D- = 0).  The oracle pins the same properties.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_04791_amd import inputs
+
+from common import max_rel_l1, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dsve():
+    from paper_1912_04791_amd import dsve as d
+    return d
+
+
+def run(dsve, wl, precision, steps=None):
+    ctx = dsve.Context.from_workload(wl, precision=precision)
+    h, q, z, t = dsve.upload(wl)
+    ctx.adot_step(h, q, z, wl.steps if steps is None else steps, t)
+    ctx.sync()
+    out = tuple(x.cpu().numpy() for x in (h, q, z, t))
+    ctx.close()
+    return out
+
+
+# Still water over an uneven bed: q = 0 and h + z = 1 stay so.  In FP64 to rounding, as in the
+# oracle; the mixed form takes the jumps to FP32 before the quadrature, so a jump of h cancels
+# one of z only to FP32 rounding (about 1e-8 of the bed's relief per edge and step).
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-13), ("mixed", 2e-6)])
+@pytest.mark.parametrize("n_cells", [400, 5000])   # channel-resident and per-step kernels
+def test_lake_at_rest_is_preserved(torch_dev, dsve, precision, bar, n_cells):
+    wl = inputs.make_lake_at_rest(n_cells=n_cells, steps=300)
+    h, q, z, t = run(dsve, wl, precision)
+    assert t[0] > 0
+    assert np.max(np.abs(q)) < bar
+    assert np.max(np.abs(h + z - 1.0)) < bar
+    assert np.max(np.abs(z - wl.z)) < bar
+
+
+# The c1 dam break with A_g = 0: shallow water over a 0.2 m bed step, the bed fixed.  The middle
+# speed is 0; the FP64 roots give it to rounding, the mixed form's FP32 roots to about 1e-8 of
+# c, so there the bed at the step moves by a few 1e-7 m over the run.
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-14), ("mixed", 2e-6)])
+def test_fixed_bed_riemann_problem(torch_dev, dsve, precision, bar):
+    wl = inputs.make_c1(n_cells=600, steps=150)
+    wl.Ag[:] = 0.0
+    got = run(dsve, wl, precision)
+    ref = oracle_run(wl)
+    assert max_rel_l1(got, ref) <= (1e-12 if precision == "fp64" else 1e-5)
+    assert np.max(np.abs(got[2] - wl.z)) < bar
+    assert np.max(np.abs(got[0] - wl.h)) > 1e-2   # the water moved
+
+
+# With A_g = 0 the speeds are u - c, 0 and u + c; at Fr >= 1.5 on both sides none is negative,
+# and so at every node of the segment path (q is interpolated linearly and h^(3/2) is convex, so
+# q stays above 1.5 sqrt(g) h^(3/2) along it), and
+# D- = (A dW - |A| dW) / 2 is zero up to the rounding of two sums of the size of D+: FP64
+# rounding, or in the mixed form FP32 rounding held to its parity bar.
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-13), ("mixed", 1e-5)])
+def test_supercritical_edges_over_a_fixed_bed_are_pure_upwind(torch_dev, dsve, precision, bar):
+    torch = torch_dev
+    n = 20_001
+    rng = np.random.default_rng(17)
+    hL, hR = rng.uniform(0.1, 1.0, n), rng.uniform(0.1, 1.0, n)
+    FrL, FrR = rng.uniform(1.5, 3.0, n), rng.uniform(1.5, 3.0, n)
+    qL, qR = FrL * np.sqrt(9.81 * hL) * hL, FrR * np.sqrt(9.81 * hR) * hR
+    zL, zR = rng.uniform(-0.2, 0.2, n), rng.uniform(-0.2, 0.2, n)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.0, dx=1.0, precision=precision)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (hL, qL, zL, hR, qR, zR)]
+    Dm = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+    Dp = torch.zeros_like(Dm)
+    ctx.dot_edge_fluct(*dev, Dm, Dp)
+    ctx.sync()
+    dm, dp = Dm.cpu().numpy(), Dp.cpu().numpy()
+    scale = np.abs(dp).max(axis=0)
+    assert np.all(scale > 0)
+    assert np.max(np.abs(dm).max(axis=0) / scale) < bar
+    # D+ is then the whole jump of the flux's water rows: D+_h = dq exactly up to rounding
+    np.testing.assert_allclose(dp[0], qR - qL, rtol=bar, atol=bar * np.abs(qR - qL).max())
+    ctx.close()
