@@ -198,6 +198,82 @@ def oracle_sample(wl):
     return wl.subset(chans), chans
 
 
+# Algorithmic figures of the standalone entry points: operations per unit as counted for the step
+# kernel (a node 166, a cell's CFL speed 51), HBM bytes per unit from their argument layouts.
+FLUCT_OPS_PER_EDGE = 3 * OPS_PER_NODE   # pairwise D+- at G = 3
+FLUCT_BYTES_PER_EDGE = 96               # six states read, six fluctuation components written
+CFL_OPS_PER_CELL = 51
+CFL_BYTES_PER_CELL = 16                 # h and q read (the speeds do not depend on z)
+UPDATE_BYTES_PER_CELL = 96              # h, q, z read and written, D- and D+ read (3 rows each)
+HBM_PEAK_GBS = 8000.0
+
+
+def entry_point_rates(reps: int = 20):
+    """The C ABI's standalone calls (dot_edge_fluct, cfl_reduce, cell_update), each timed alone
+    with HIP events on the stream they run on, on device-resident synthetic inputs: 2^22 random
+    edge pairs, and a single FP64 channel of 2^24 cells."""
+    import torch
+    from paper_1912_04791_amd import dsve, inputs
+    f64 = dict(dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def seconds_per_call(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def valu(units, ops, secs):
+        tf = units * ops / secs / 1e12
+        return {"bound": "alu", "achieved": tf, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP64_VALU_PEAK_TFLOPS}
+
+    def hbm(units, nbytes, secs):
+        gbs = units * nbytes / secs / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+
+    out = {}
+    n = 1 << 22
+    WL, WR = inputs.make_random_edges(n, seed=5)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.005, dx=1.0, stream=stream)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (*WL, *WR)]
+    Dm, Dp = torch.empty(3, n, **f64), torch.empty(3, n, **f64)
+    t = seconds_per_call(lambda: ctx.dot_edge_fluct(*dev, Dm, Dp))
+    ctx.sync()
+    ctx.close()
+    out["dot_edge_fluct"] = {"edges": n, "us_per_call": t * 1e6, "edges_per_s": n / t,
+                             "roofline": valu(n, FLUCT_OPS_PER_EDGE, t),
+                             "hbm_GB_per_s": n * FLUCT_BYTES_PER_EDGE / t / 1e9}
+    del dev, Dm, Dp
+
+    N = 1 << 24
+    rng = np.random.default_rng(6)
+    h = torch.from_numpy(1.0 + 0.1 * rng.random(N)).cuda()
+    q = 0.4 * h
+    z = torch.zeros(N, **f64)
+    ctx = dsve.Context.single(N, porosity=0.4, A_g=0.005, dx=0.01, stream=stream)
+    amax, dt = torch.zeros(1, **f64), torch.zeros(1, **f64)
+    t = seconds_per_call(lambda: ctx.cfl_reduce(h, q, z, amax, dt))
+    out["cfl_reduce"] = {"cells": N, "us_per_call": t * 1e6, "cells_per_s": N / t,
+                         "roofline": valu(N, CFL_OPS_PER_CELL, t),
+                         "hbm_GB_per_s": N * CFL_BYTES_PER_CELL / t / 1e9}
+    Dm = torch.from_numpy(1e-3 * rng.standard_normal((3, N + 1))).cuda()
+    Dp = torch.from_numpy(1e-3 * rng.standard_normal((3, N + 1))).cuda()
+    dt.fill_(1e-6)
+    t = seconds_per_call(lambda: ctx.cell_update(Dm, Dp, dt, h, q, z))
+    ctx.sync()
+    ctx.close()
+    out["cell_update"] = {"cells": N, "us_per_call": t * 1e6, "cells_per_s": N / t,
+                          "roofline": hbm(N, UPDATE_BYTES_PER_CELL, t)}
+    return out
+
+
 def cpu_baseline(wl, budget_s: float = 12.0):
     """The oracle as it stands, on this host's cores, on a bounded sample of the same
     workload.  Returns the baseline dict, the oracle state and the sample description."""
@@ -257,6 +333,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=-1)
     ap.add_argument("--cfl-split", type=int, default=0,
                     help="CFL sub-slots per channel with an explicit launch (0 = automatic)")
+    ap.add_argument("--no-entry", action="store_true",
+                    help="skip timing the standalone entry points")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
@@ -369,6 +447,13 @@ def main():
                            "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
                                       "graph_steps": r["launch"][2], "cfl_split": r["launch"][3]},
                            "adot_fp64_speedup": (adot64["edge_updates_per_s"] / v) if adot64 else None}
+
+    if not args.no_entry:
+        out["entry_points"] = entry_point_rates()
+        for k, v in out["entry_points"].items():
+            r = v["roofline"]
+            print(f"[bench] {k}: {v['us_per_call']:.1f} us/call, {r['achieved']:.2f} {r['unit']} "
+                  f"({r['frac']:.2f} of {r['bound']} peak)", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         base, ref, n, chans = cpu_baseline(wl)

@@ -41,6 +41,7 @@ enum { CL_GRASS = LAW_GRASS, CL_GRASS_THR = LAW_GRASS_THR, CL_POWER = LAW_POWER,
 
 constexpr int kMaxGauss = 5;
 constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most
+constexpr int kCflThreads = 1024;  // threads per workgroup of the CFL-maximum kernel
 // Waves per SIMD the step kernel is compiled for (bounds its registers per lane).
 #ifndef DSVE_MINW_FP64
 #define DSVE_MINW_FP64 3

@@ -432,40 +432,62 @@ __device__ __forceinline__ int find_channel(const int64_t *off, int C, int64_t i
 // time and flushes it with one global atomic when the channel changes (cells are visited in
 // increasing order within a workgroup, so channels change monotonically).
 template <int PREC, int CL>
-__global__ __launch_bounds__(256) void k_cfl(CflArgs A)
+__global__ __launch_bounds__(kCflThreads) void k_cfl(CflArgs A)
 {
+    // Each workgroup takes a contiguous range of cells, kCflThreads at a time.  Every lane keeps
+    // the running maximum of its cells in its wave's current channel `cur` (wave-uniform); the
+    // lanes are reduced across only when one of them reaches another channel, and at the end.
+    // The workgroup's home channel (that of its first cell) collects in LDS and is merged into
+    // its slot once; other channels go to their slots directly.  Workgroups of 1024 threads keep
+    // those end-of-kernel merges, which serialise on one address, to a few hundred.
     __shared__ unsigned long long s_acc;
-    unsigned long long reg_acc = 0ull;   // thread 0 only
-    int reg_chan = -1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < A.n_cells; i0 += stride) {
+    const int lane = threadIdx.x & 63;
+    const int64_t per =
+        ((A.n_cells + gridDim.x - 1) / gridDim.x + kCflThreads - 1) / kCflThreads * kCflThreads;
+    const int64_t start = (int64_t)blockIdx.x * per;
+    const int64_t end = start + per < A.n_cells ? start + per : A.n_cells;
+    if (threadIdx.x == 0) s_acc = 0ull;
+    __syncthreads();
+    if (start >= end) return;   // the same for the whole workgroup
+    const int home = find_channel(A.off, A.n_channels, start);
+    int c = home;                  // channel of this lane's cell
+    int cur = home;                // the wave's current channel
+    unsigned long long acc = 0ull; // this lane's maximum over its cells in `cur`
+    bool bad = false;
+    for (int64_t i0 = start; i0 < end; i0 += kCflThreads) {
         const int64_t i = i0 + threadIdx.x;
-        const bool active = i < A.n_cells;
-        const int home = find_channel(A.off, A.n_channels, i0);
-        if (threadIdx.x == 0) s_acc = 0ull;
-        __syncthreads();
-        int c = home;
+        const bool active = i < end;
         unsigned long long bits = 0ull;
-        bool bad = false;
         if (active) {
             while (i >= A.off[c + 1]) ++c;
             const double sp = fabs(cell_speed<PREC, CL>(A.h[i], A.q[i], A.g, closure_of(A.ch[c]), bad));
             bits = (unsigned long long)__double_as_longlong(sp);
         }
-        raise_flag(A.flags, bad);
-        reduce_channel_max(bits, c, active, home, &s_acc, A.amax);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (home != reg_chan) {
-                if (reg_chan >= 0) flush_max(&A.amax[reg_chan], reg_acc);
-                reg_chan = home;
-                reg_acc = s_acc;
-            } else {
-                reg_acc = (s_acc > reg_acc) ? s_acc : reg_acc;
+        const unsigned long long moved = __ballot(active && c != cur);
+        if (moved == 0ull) {
+            if (active) acc = bits > acc ? bits : acc;
+        } else {
+            // the wave leaves `cur`: merge what its lanes hold for it, then this round's cells
+            // by channel, and go on in the channel of its last active lane
+            const unsigned long long m = wave_max_u64(acc);
+            if (lane == 0 && m != 0ull) {
+                if (cur == home) atomicMax(&s_acc, m);
+                else flush_max(&A.amax[cur], m);
             }
+            acc = 0ull;
+            reduce_channel_max(bits, c, active, home, &s_acc, A.amax);
+            const unsigned long long act = __ballot(active);
+            cur = __shfl(c, 63 - __clzll((long long)act), 64);
         }
     }
-    if (threadIdx.x == 0 && reg_chan >= 0) flush_max(&A.amax[reg_chan], reg_acc);
+    const unsigned long long m = wave_max_u64(acc);
+    if (lane == 0 && m != 0ull) {
+        if (cur == home) atomicMax(&s_acc, m);
+        else flush_max(&A.amax[cur], m);
+    }
+    raise_flag(A.flags, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_acc != 0ull) flush_max(&A.amax[home], s_acc);
 }
 
 template <int G, int PREC, int CL>
@@ -532,8 +554,8 @@ static inline unsigned int blocks_for(int64_t n, int bs)
 // global atomics (serialised on one address per channel) stay cheap.
 static inline unsigned int cfl_grid(int64_t n_cells)
 {
-    const unsigned int full = blocks_for(n_cells, 256);
-    return full < 2048u ? full : 2048u;
+    const unsigned int full = blocks_for(n_cells, kCflThreads);
+    return full < 512u ? full : 512u;
 }
 
 // Dispatch over the compile-time variants: G in [1, 5] quadrature points, closure (law).
@@ -653,7 +675,7 @@ hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile
 template <int PREC>
 static hipError_t launch_cfl_prec(const CflArgs &a, int cl, hipStream_t stream)
 {
-    const dim3 grid(cfl_grid(a.n_cells)), block(256);
+    const dim3 grid(cfl_grid(a.n_cells)), block(kCflThreads);
 #define DSVE_LAUNCH_CFL(CC) hipLaunchKernelGGL((k_cfl<PREC, CC>), grid, block, 0, stream, a)
     DSVE_DISPATCH_CL(cl, DSVE_LAUNCH_CFL)
 #undef DSVE_LAUNCH_CFL
