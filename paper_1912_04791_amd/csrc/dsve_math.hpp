@@ -167,7 +167,9 @@ __device__ __forceinline__ Closure closure_of(const ChanInfo &ci)
     return Closure{ci.kqg, ci.K1, ci.K2, ci.lp0, ci.lp1, ci.law, ci.ipow};
 }
 
-__device__ __forceinline__ double m_pow(double a, double b) { return pow(a, b); }
+// FP64 power a^b, a > 0, as 2^(b log2 a): a relative error of about 2 |b log2 a| ulp, a few ulp
+// at the laws' speeds, at well under half the cost of the library pow
+__device__ __forceinline__ double m_pow(double a, double b) { return exp2(b * log2(a)); }
 // FP32 power of the mixed form, a >= 0, b > 0: 2^(b log2 a) from the hardware base-2 logarithm
 // and exponential (relative error about 1e-6 for the exponents of the laws; a = 0 gives 0)
 __device__ __forceinline__ float m_pow(float a, float b)

@@ -168,3 +168,16 @@ def test_stress_law_derivatives_without_reciprocal_of_q():
     vr_r = np.where(tt > 0, lp1 * np.maximum(tt, 0) ** 1.1 * (lp0 * np.abs(u) * r / h), 0)
     np.testing.assert_allclose(vr_r, vr_q, rtol=1e-14)
     assert np.count_nonzero(mpm_q) > 1000 and np.count_nonzero(vr_q) > 1000
+
+
+def test_power_as_exp2_of_log2():
+    # a^b = 2^(b log2 a) for the power law with a non-integer exponent (FP64 form): the rounding of
+    # log2 a and of the product each leave y = b log2 a an absolute error up to about |y| 2^-53,
+    # so the power's relative error is about 2 |y| ln2 2^-53: a few ulp at the speeds of the laws
+    # (|y| of a few units), 1e-14 at the far end of this range
+    a = np.concatenate([np.logspace(-4, 1.5, 20001), np.linspace(0.5, 2.0, 2001)])
+    for b in (1.5, 2.5, 5.5, 9.5):
+        y = b * np.log2(a)
+        got = np.exp2(y)
+        bound = (2 * np.abs(y) * np.log(2) + 4) * 2.0 ** -53
+        assert np.all(np.abs(got / a ** b - 1) <= bound), b
