@@ -58,7 +58,7 @@ typedef enum {
     DSVE_E_HIP = -2,            /* a HIP runtime call failed */
     DSVE_E_NONFINITE = -3,      /* a CFL speed was NaN/Inf or zero (e.g. h <= 0, coalescing roots) */
     DSVE_E_NONHYPERBOLIC = -4,  /* arccos argument outside [-1-1e-12, 1+1e-12] or k1 <= 0 */
-    DSVE_E_UNSUPPORTED = -5     /* a valid request this build does not implement */
+    DSVE_E_UNSUPPORTED = -5     /* a valid request the library does not implement */
 } dsve_status;
 
 /* Boundary conditions: the ghost state W_{-1} (left) or W_N (right), from the adjacent cell

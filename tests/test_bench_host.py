@@ -63,3 +63,13 @@ def test_profile_calibration_is_the_first_copy(tmp_path):
     out, first = profsum.counters(str(tmp_path), "k_step<3, 0, 0, false>")
     assert first["FETCH_SIZE"] == 131092.0
     assert sorted(out["FETCH_SIZE"]) == [500.0, 520.0]
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr and out.stdout == ""
