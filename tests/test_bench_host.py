@@ -73,3 +73,11 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                          capture_output=True, text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU" in out.stderr and out.stdout == ""
+
+
+def test_alu_roofline_peaks():
+    fp64 = bench.alu_roofline("fp64", 20.0)
+    assert fp64["peak"] == 78.6 and abs(fp64["frac"] - 20.0 / 78.6) < 1e-12
+    mixed = bench.alu_roofline("mixed", 30.0)
+    assert mixed["peak"] == 157.3 and abs(mixed["frac"] - 30.0 / 157.3) < 1e-12
+    assert mixed["peak_nonpacked"] == 78.6 and abs(mixed["frac_nonpacked"] - 30.0 / 78.6) < 1e-12
