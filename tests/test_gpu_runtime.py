@@ -202,3 +202,43 @@ def test_wide_index_path_sampled_channels(torch_dev, dsve):
     wl = inputs.make_c4(n_channels=16384, len_lo=32768, len_hi=32768, steps=3)
     assert wl.n_cells + wl.n_channels >= 2 ** 29
     _sampled_channels_check(dsve, wl, "fp64", 1e-12, every=2048, launch=(256, 32, 0))
+
+
+def test_pairwise_fluct_past_32_bit_offsets(torch_dev, dsve):
+    # 2^30 + 7 edges: row 2 of the fluctuations starts past element 2^31 (byte 2^34), so every
+    # offset of that row needs 64-bit arithmetic; about 103 GB of device memory.  The edge states
+    # come from a seeded device generator (the recipe of make_random_edges); 4096 sampled edges
+    # are checked against the oracle at the FP64 bar.
+    torch = torch_dev
+    n = (1 << 30) + 7
+    f64 = dict(dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(1234)
+    def uni(lo, hi):
+        return torch.rand(n, generator=gen, **f64) * (hi - lo) + lo
+    hL = uni(0.05, 5.0)
+    uL = uni(-3.0, 3.0)
+    zL = uni(-1.0, 1.0)
+    hR = hL * (1.0 + 0.3 * uni(-1.0, 1.0))
+    uR = uL + 0.3 * uni(-1.0, 1.0)
+    zR = zL + 0.3 * uni(-1.0, 1.0)
+    qL = hL * uL
+    del uL
+    qR = hR * uR
+    del uR
+    Dm = torch.empty(3, n, **f64)
+    Dp = torch.empty(3, n, **f64)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.02, dx=1.0)
+    ctx.dot_edge_fluct(hL, qL, zL, hR, qR, zR, Dm, Dp)
+    ctx.sync()
+    ctx.close()
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 4000), np.arange(n - 96, n)]))
+    ti = torch.from_numpy(idx).cuda()
+    WL = tuple(a[ti].cpu().numpy() for a in (hL, qL, zL))
+    WR = tuple(a[ti].cpu().numpy() for a in (hR, qR, zR))
+    gm, gp = Dm[:, ti].cpu().numpy(), Dp[:, ti].cpu().numpy()
+    del hL, qL, zL, hR, qR, zR, Dm, Dp, ti
+    torch.cuda.empty_cache()
+    rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, 0.02)
+    for got, ref in ((gm, rm), (gp, rp)):
+        assert np.abs(got - ref).sum() <= 1e-12 * np.abs(ref).sum()
