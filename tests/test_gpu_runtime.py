@@ -242,3 +242,30 @@ def test_pairwise_fluct_past_32_bit_offsets(torch_dev, dsve):
     rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, 0.02)
     for got, ref in ((gm, rm), (gp, rp)):
         assert np.abs(got - ref).sum() <= 1e-12 * np.abs(ref).sum()
+
+
+@pytest.mark.parametrize("where", ["middle", "last"])
+def test_cfl_reduce_past_32_bit_cell_indices(torch_dev, dsve, where):
+    # 2^31 + 3 cells of one state, with one faster cell planted past index 2^31: the maximum is
+    # that cell's speed, whatever the kernel's ranges and their 64-bit arithmetic (about 103 GB
+    # of device memory with the context's own copy of the state)
+    torch = torch_dev
+    N = (1 << 31) + 3
+    f64 = dict(dtype=torch.float64, device="cuda")
+    h = torch.full((N,), 1.0, **f64)
+    q = torch.full((N,), 0.5, **f64)
+    z = torch.zeros(N, **f64)
+    k = (1 << 31) + 1 if where == "middle" else N - 1
+    h[k], q[k] = 2.0, 3.0
+    ctx = dsve.Context.single(N, porosity=0.4, A_g=0.01, dx=1.0)
+    amax, dt = torch.zeros(1, **f64), torch.zeros(1, **f64)
+    ctx.cfl_reduce(h, q, z, amax, dt)
+    ctx.sync()
+    ctx.close()
+    del h, q, z
+    torch.cuda.empty_cache()
+    xi = 1.0 / 0.6
+    base = oracle.cfl_amax(np.array([1.0]), np.array([0.5]), np.array([0.0]), 9.81, xi, 0.01)
+    fast = oracle.cfl_amax(np.array([2.0]), np.array([3.0]), np.array([0.0]), 9.81, xi, 0.01)
+    assert fast > base
+    assert abs(float(amax[0]) - fast) <= 1e-14 * fast
