@@ -196,7 +196,8 @@ dsve_status dot_edge_fluct(dsve_ctx *ctx, const double *hL, const double *qL, co
  *   W_i <- W_i - (dt/dx) (Dm[:, i+1] + Dp[:, i]) + dt S(W_i)
  * with Dm, Dp the [3][N+1] edge fluctuations (edge i is the left face of cell i),
  * dt_dev a device pointer to the time step, S the friction source of the context (zero
- * when ks = 0), and h, q, z updated in place.  Single-channel contexts only. */
+ * when ks = 0), and h, q, z updated in place.  The six arrays and dt_dev must not
+ * overlap one another.  Single-channel contexts only. */
 dsve_status cell_update(dsve_ctx *ctx, const double *Dm, const double *Dp, const double *dt_dev,
                         double *h, double *q, double *z);
 
