@@ -61,6 +61,22 @@ def counters(pmc_dir: str, kernel: str):
     return out, first
 
 
+def timing_note(events_us: str, traced_us: float) -> str:
+    """How the traced average relates to bench.py's events figure (a value or a range)."""
+    top = max(float(x) for x in events_us.replace("\u2013", "-").split("-") if x.strip())
+    head = (f"`bench.py` times this kernel at {events_us} us per step with HIP events over "
+            "graph-replayed steps on the stream it runs on (a range spans several boxes); the "
+            "roofline it reports uses that figure.")
+    if traced_us > 1.02 * top:
+        return head + (f" The traced average above ({traced_us:.2f} us) is higher because under "
+                       "the kernel trace each dispatch is timestamped on its own and consecutive "
+                       "dispatches run back to back, which removes the overlap of one kernel's "
+                       "tail with the next kernel's start that graph replays otherwise get.")
+    return head + (f" The traced average above ({traced_us:.2f} us) agrees with it within 2%: at "
+                   "this step length the overlap of one kernel's tail with the next kernel's "
+                   "start, which the trace removes, is too small to show.")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--name", required=True)
@@ -75,6 +91,8 @@ def main():
     ap.add_argument("--cmd", required=True, help="the profiling commands, verbatim")
     ap.add_argument("--algorithmic-bytes", type=float, default=None)
     ap.add_argument("--edges", type=int, default=None)
+    ap.add_argument("--events-us", default=None,
+                    help="the kernel's step time from bench.py's HIP events, e.g. 26.5-28.5")
     args = ap.parse_args()
 
     import sys
@@ -133,6 +151,8 @@ def main():
             entry["valu_insts_per_edge"] = per
             lines.append(f"- VALU instructions per edge update: {per:.0f} "
                          f"(algorithmic operation count {ops_per_edge_update()})")
+    if args.events_us:
+        lines += ["", "## Timing note", "", timing_note(args.events_us, st["avg_ns"] / 1e3)]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"{args.name}.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")

@@ -81,3 +81,10 @@ def test_alu_roofline_peaks():
     mixed = bench.alu_roofline("mixed", 30.0)
     assert mixed["peak"] == 157.3 and abs(mixed["frac"] - 30.0 / 157.3) < 1e-12
     assert mixed["peak_nonpacked"] == 78.6 and abs(mixed["frac_nonpacked"] - 30.0 / 78.6) < 1e-12
+
+
+def test_profile_timing_note_wording():
+    from paper_1912_04791_amd import profsum
+    assert "is higher" in profsum.timing_note("26.5-28.5", 33.4)
+    assert "agrees with it within 2%" in profsum.timing_note("398", 399.5)
+    assert "agrees with it within 2%" in profsum.timing_note("415", 412.4)
