@@ -177,7 +177,7 @@ def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: s
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1)
     res = {"ms_total": ms, "wall_s": wall, "launch": (*ctx.get_launch(), ctx.get_cfl_split()),
-           "cus": ctx.device_cus()}
+           "cus": ctx.device_cus(), "resident": ctx.get_resident()}
     ctx.close()
     return res
 
@@ -427,7 +427,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {**alu_roofline(main_prec, achieved_tflops),
                      "traffic": traffic,
-                     "kernel": f"k_step<{wl.n_gauss}, {'FP64' if main_prec == 'fp64' else 'MIXED'}, {form}>",
+                     "kernel": (f"{'k_resident' if main['resident'] else 'k_step'}<{wl.n_gauss}, "
+                                f"{'FP64' if main_prec == 'fp64' else 'MIXED'}, {form}>"),
                      "ops_per_edge_update": ops,
                      "valu_issue": valu_issue(wl.name, main_prec, edges, main["ms_per_step"])},
     }
