@@ -124,7 +124,14 @@ def valu_issue(workload: str, precision: str, edges: int, ms_per_step: float):
         return None
     per_edge = ent["valu_insts_per_edge"]
     busy_s = per_edge * edges / 64.0 * CYCLES_PER_WAVE_INST / SIMDS / CLOCK_HZ
-    return {"insts_per_edge": per_edge, "frac": busy_s / (ms_per_step * 1e-3)}
+    out = {"insts_per_edge": per_edge, "frac": busy_s / (ms_per_step * 1e-3)}
+    if "valu_active_per_edge" in ent:
+        # the VALU-active counter (4-cycle units), which also counts the extra cycles of
+        # quarter-rate instructions: the share of the SIMDs' cycles spent issuing VALU work
+        act_s = ent["valu_active_per_edge"] * edges / 64.0 * CYCLES_PER_WAVE_INST / SIMDS / CLOCK_HZ
+        out["active_per_edge"] = ent["valu_active_per_edge"]
+        out["active_frac"] = act_s / (ms_per_step * 1e-3)
+    return out
 
 
 def alu_roofline(precision: str, achieved_tflops: float) -> dict:

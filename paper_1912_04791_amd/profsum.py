@@ -151,6 +151,12 @@ def main():
             entry["valu_insts_per_edge"] = per
             lines.append(f"- VALU instructions per edge update: {per:.0f} "
                          f"(algorithmic operation count {ops_per_edge_update()})")
+        if args.edges and "SQ_ACTIVE_INST_VALU" in c:
+            # cycles the waves spend issuing VALU instructions, in units of 4 cycles: above the
+            # instruction count where quarter-rate (transcendental) instructions hold the SIMD
+            act = statistics.median(c["SQ_ACTIVE_INST_VALU"]) * 64 / args.edges
+            entry["valu_active_per_edge"] = act
+            lines.append(f"- VALU-active 4-cycle units per edge update: {act:.0f}")
     if args.events_us:
         lines += ["", "## Timing note", "", timing_note(args.events_us, st["avg_ns"] / 1e3)]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)

@@ -42,7 +42,13 @@ def test_valu_issue_share_from_the_counter_summary(tmp_path, monkeypatch):
     busy = 2 ** 14 * 640 * 4 / 1024 / 2.4e9
     v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
     assert v["insts_per_edge"] == 640.0 and abs(v["frac"] - 0.5) < 1e-12
+    assert "active_frac" not in v
     assert bench.valu_issue("c3", "fp64", 2 ** 20, 1.0) is None
+    # with the VALU-active counter: 704 four-cycle units per edge is 1.1 times the issue time
+    ent["valu_active_per_edge"] = 704.0
+    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ent}))
+    v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
+    assert abs(v["active_frac"] - 0.55) < 1e-12 and v["active_per_edge"] == 704.0
 
 
 def test_profile_calibration_is_the_first_copy(tmp_path):
