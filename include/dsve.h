@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define DSVE_ABI_VERSION 4
+#define DSVE_ABI_VERSION 5
 
 typedef struct dsve_ctx dsve_ctx;
 
@@ -56,8 +56,12 @@ typedef enum {
     DSVE_OK = 0,
     DSVE_E_ARG = -1,            /* invalid argument (null pointer, size, parameter range) */
     DSVE_E_HIP = -2,            /* a HIP runtime call failed */
-    DSVE_E_NONFINITE = -3,      /* a CFL speed was NaN/Inf or zero (e.g. h <= 0, coalescing roots) */
-    DSVE_E_NONHYPERBOLIC = -4,  /* arccos argument outside [-1-1e-12, 1+1e-12] or k1 <= 0 */
+    DSVE_E_NONFINITE = -3,      /* a CFL speed was NaN/Inf or zero (e.g. h <= 0), or a non-finite
+                                   arccos argument (an overflowed or NaN state) */
+    DSVE_E_NONHYPERBOLIC = -4,  /* arccos argument outside [-1-1e-12, 1+1e-12] or k1 <= 0 (complex
+                                   roots, Sec. 3.3), or exactly +-1 at a quadrature node: two
+                                   eigenvalues coalesce to working precision and R^-1 (Eq. RR-1)
+                                   does not exist (e.g. a fixed bed at Fr = +-1) */
     DSVE_E_UNSUPPORTED = -5     /* a valid request the library does not implement */
 } dsve_status;
 
@@ -212,8 +216,12 @@ dsve_status cfl_reduce(dsve_ctx *ctx, const double *h, const double *q, const do
 /* Advance one channel by n_steps >= 0 time steps in place: per step, ghost
  * cells from the boundary conditions, dt = cfl*dx/amax(W^n), DOT fluctuations
  * at every edge, cell update with the friction source, and the CFL speed of W^{n+1} --
- * one fused kernel per step, replayed from a HIP graph, or one launch for the whole run
- * when the run is channel-resident (dsve_set_resident).  *t_dev (device) is
+ * one fused kernel per step, or one launch for the whole run when the run is
+ * channel-resident (dsve_set_resident).  With graph_steps > 0 (dsve_set_launch) the steps
+ * are replayed from captured HIP graphs: n_steps / graph_steps replays of a graph of
+ * graph_steps steps, then one replay of a graph of the remaining n_steps % graph_steps
+ * steps; the graphs are captured at the first run that needs them and kept while the
+ * arrays and the launch configuration stay the same (dsve_prepare_run captures them ahead).  *t_dev (device) is
  * increased by the sum of the time steps.  The result is in (h, q, z) when the
  * enqueued work completes, bitwise independent of the launch configuration. */
 dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps, double *t_dev);
@@ -224,6 +232,19 @@ dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_step
  * launch for the whole run when it is channel-resident. */
 dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
                               double *t_dev);
+
+/* Capture ahead the HIP graphs a run of n_steps on these arrays will replay (see adot_step),
+ * so that the run itself only replays them: graph capture and instantiation then fall
+ * outside a timed or latency-critical region.  Enqueues no work; the arrays are not read.
+ * Nothing to do for channel-resident runs or with graph_steps = 0. */
+dsve_status dsve_prepare_run(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                             double *t_dev);
+
+/* How the last run (adot_step, adot_step_batched) was launched: *graph_launches HIP graph
+ * replays covering *graph_steps steps, and *direct_launches kernels launched one by one (step
+ * kernels, or 1 for a channel-resident run).  Any pointer may be NULL. */
+dsve_status dsve_get_last_run(const dsve_ctx *ctx, int *graph_launches, int *graph_steps,
+                              int *direct_launches);
 
 /* Wait for the context's queued work; report a deferred device error
  * (DSVE_E_NONFINITE, DSVE_E_NONHYPERBOLIC) raised since the last sync. */

@@ -269,7 +269,10 @@ void or_flux_matrix(const double W[3], const or_phys *p, double A[9])
  * Fr = u/c keeps its sign (reading: the formulas are used for u < 0 too).
  * The arccos argument is clamped to [-1, 1]; if it lies further than 1e-12
  * outside, or k1 <= 0, *nonhyp is set (the roots would not be real; this
- * cannot happen for the Grass law with A_g >= 0). */
+ * cannot happen for the Grass law with A_g >= 0).  When R^-1 is asked for and two
+ * stored eigenvalues are equal, *nonhyp is set too: the denominators of Eq. RR-1
+ * vanish and R^-1 does not exist (the eigenvalues are distinct for a movable bed,
+ * Sec. 3.3; with a fixed bed they coalesce at Fr = +-1). */
 int or_eigensystem(const double W[3], const or_phys *p, double lam[3], double R[9], double Rinv[9],
                    int *nonhyp)
 {
@@ -309,6 +312,7 @@ int or_eigensystem(const double W[3], const or_phys *p, double lam[3], double R[
             int k = (i < 2) ? i + 2 : i - 1;
             double li = lam[i - 1], lj = lam[j - 1], lk = lam[k - 1];
             double den = (li - lj) * (li - lk);
+            if (nonhyp && den == 0.0) *nonhyp = 1;
             Rinv[(i - 1) * 3 + 0] = (c2 - u * u + lj * lk) / den;
             Rinv[(i - 1) * 3 + 1] = (2.0 * u - lj - lk) / den;
             Rinv[(i - 1) * 3 + 2] = c2 / den;

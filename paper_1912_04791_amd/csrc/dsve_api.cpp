@@ -3,10 +3,11 @@
 // A context owns: per-channel records and edge offsets on the device, the tile table of the
 // fused step kernel, one ping-pong copy of the state and clocks, three rotating CFL-maximum slots
 // (each with up to 4 sub-slots per channel), a flag word for deferred device errors, and a cached
-// HIP graph of `graph_steps` fused steps.  A run of n steps is: clear slots -> CFL max of W^0
-// into slot 0 -> graph replays (each node is one step kernel; slot and ping-pong phase repeat
-// every 6 steps, so graph_steps is a multiple of 6) -> leftover steps launched directly -> copy
-// back when n is odd.  When every channel has at most kResidentCells cells the run is instead
+// HIP graph of `graph_steps` fused steps, plus a few graphs of shorter lengths.  A run of n steps
+// is: clear slots -> CFL max of W^0 into slot 0 -> n / graph_steps replays of the main graph
+// (each node is one step kernel; slot and ping-pong phase repeat every 6 steps, so graph_steps
+// is a multiple of 6) -> one replay of the graph of the remaining n % graph_steps steps -> copy
+// back when n is odd.  With graph_steps = 0 every step is launched directly.  When every channel has at most kResidentCells cells the run is instead
 // one channel-resident launch for all n steps.
 #include <hip/hip_runtime.h>
 
@@ -63,9 +64,17 @@ struct dsve_ctx {
     int64_t n_tiles = 0;
     int table_tile = 0;
 
+    // captured graphs, valid for the buffers and launch in g_key / g_*: the main graph of
+    // graph_steps steps, and graphs of the remainders n % graph_steps of recent run lengths
     hipGraphExec_t gexec = nullptr;
+    struct RemGraph { hipGraphExec_t exec = nullptr; int steps = 0; };
+    RemGraph rem[4];
+    int rem_next = 0;
+    bool g_keyed = false;
     const void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
     int g_steps = 0, g_tile = 0, g_grid = 0, g_split = 0;
+    // the last run: graph replays, the steps they ran, steps launched directly
+    int last_graph_launches = 0, last_graph_steps = 0, last_direct = 0;
 
     int last_amax_slot = -1;   // slot holding the CFL max of the latest state, or -1
     dsve_status sticky = DSVE_OK;
@@ -162,6 +171,11 @@ static void free_graph(dsve_ctx *c)
 {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
+    for (auto &r : c->rem) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        r = dsve_ctx::RemGraph{};
+    }
+    c->g_keyed = false;
     c->g_steps = 0;
 }
 
@@ -546,18 +560,13 @@ static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z,
     return a;
 }
 
-static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, double *t)
+// Capture steps 0..n-1 of a run on (h, q, z, t) into an executable graph.
+static dsve_status capture_steps(dsve_ctx *ctx, int n, int grid, double *h, double *q, double *z,
+                                 double *t, hipGraphExec_t *out)
 {
-    const int grid = grid_of(ctx);
-    const void *key[4] = {h, q, z, t};
-    const int split = split_of(ctx, grid);
-    if (ctx->gexec && ctx->g_steps == ctx->graph_steps && ctx->g_tile == ctx->tile &&
-        ctx->g_grid == grid && ctx->g_split == split && std::equal(key, key + 4, ctx->g_key))
-        return DSVE_OK;
-    free_graph(ctx);
     hipGraph_t graph = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < ctx->graph_steps; ++j) {
+    for (int j = 0; j < n; ++j) {
         hipError_t e = launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
                                    ctx->tile, grid, ctx->cap_stream);
         if (e != hipSuccess) {
@@ -567,17 +576,59 @@ static dsve_status ensure_graph(dsve_ctx *ctx, double *h, double *q, double *z, 
         }
     }
     HIP_TRY(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
-    hipError_t e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        ctx->gexec = nullptr;
+        *out = nullptr;
         return fail(ctx, DSVE_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
-    ctx->g_steps = ctx->graph_steps;
-    ctx->g_tile = ctx->tile;
-    ctx->g_grid = grid;
-    ctx->g_split = split;
-    std::copy(key, key + 4, ctx->g_key);
+    return DSVE_OK;
+}
+
+static hipGraphExec_t find_rem(const dsve_ctx *ctx, int steps)
+{
+    for (const auto &r : ctx->rem)
+        if (r.exec && r.steps == steps) return r.exec;
+    return nullptr;
+}
+
+// The graphs a run of n_steps on (h, q, z, t) replays: the main graph when n_steps >= graph_steps,
+// and the graph of the remaining n_steps % graph_steps steps (every run starts at phase 0 and
+// the main graph spans whole 6-step periods, so the remainder also starts at phase 0).  Graphs
+// are kept while the buffers and the launch stay the same.
+static dsve_status ensure_graphs(dsve_ctx *ctx, double *h, double *q, double *z, double *t,
+                                 int n_steps)
+{
+    const int grid = grid_of(ctx);
+    const void *key[4] = {h, q, z, t};
+    const int split = split_of(ctx, grid);
+    if (!(ctx->g_keyed && ctx->g_steps == ctx->graph_steps && ctx->g_tile == ctx->tile &&
+          ctx->g_grid == grid && ctx->g_split == split && std::equal(key, key + 4, ctx->g_key))) {
+        free_graph(ctx);
+        ctx->g_keyed = true;
+        ctx->g_steps = ctx->graph_steps;
+        ctx->g_tile = ctx->tile;
+        ctx->g_grid = grid;
+        ctx->g_split = split;
+        std::copy(key, key + 4, ctx->g_key);
+    }
+    const int GS = ctx->graph_steps;
+    if (n_steps >= GS && !ctx->gexec) {
+        dsve_status st = capture_steps(ctx, GS, grid, h, q, z, t, &ctx->gexec);
+        if (st != DSVE_OK) return st;
+    }
+    const int r = n_steps % GS;
+    if (r > 0 && !find_rem(ctx, r)) {
+        auto &slot = ctx->rem[ctx->rem_next];
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot = dsve_ctx::RemGraph{};
+        hipGraphExec_t ex = nullptr;
+        dsve_status st = capture_steps(ctx, r, grid, h, q, z, t, &ex);
+        if (st != DSVE_OK) return st;
+        slot.exec = ex;
+        slot.steps = r;
+        ctx->rem_next = (ctx->rem_next + 1) % (int)(sizeof ctx->rem / sizeof ctx->rem[0]);
+    }
     return DSVE_OK;
 }
 
@@ -601,27 +652,42 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
         HIP_TRY(ctx, launch_resident(a, ctx->precision, ctx->G, ctx->cl, ctx->resident_threads, grid,
                                      ctx->stream));
         ctx->last_amax_slot = 0;
+        ctx->last_graph_launches = 0;
+        ctx->last_graph_steps = 0;
+        ctx->last_direct = 1;
         return DSVE_OK;
     }
     dsve_status st = build_tile_table(ctx, ctx->tile);
     if (st != DSVE_OK) return st;
+    if (ctx->graph_steps > 0) {
+        st = ensure_graphs(ctx, h, q, z, t, n_steps);   // before any work of the run is enqueued
+        if (st != DSVE_OK) return st;
+    }
     // slots: clear all three, CFL max of W^0 into sub-slot 0 of slot 0
     HIP_TRY(ctx, launch_fill_u64(ctx->d_amax, 3 * ctx->amax_slot, 0ull, ctx->stream));
     st = enqueue_cfl(ctx, h, q, z, ctx->d_amax);
     if (st != DSVE_OK) return st;
-    int done = 0;
-    if (ctx->graph_steps > 0 && n_steps >= ctx->graph_steps) {
-        st = ensure_graph(ctx, h, q, z, t);
-        if (st != DSVE_OK) return st;
+    int done = 0, launches = 0;
+    if (ctx->graph_steps > 0) {
         while (n_steps - done >= ctx->graph_steps) {
             HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
             done += ctx->graph_steps;
+            ++launches;
+        }
+        if (done < n_steps) {
+            HIP_TRY(ctx, hipGraphLaunch(find_rem(ctx, n_steps - done), ctx->stream));
+            done = n_steps;
+            ++launches;
         }
     }
+    const int graph_done = done;
     const int grid = grid_of(ctx);
     for (int j = done; j < n_steps; ++j)
         HIP_TRY(ctx, launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
                                  ctx->tile, grid, ctx->stream));
+    ctx->last_graph_launches = launches;
+    ctx->last_graph_steps = graph_done;
+    ctx->last_direct = n_steps - graph_done;
     if (n_steps % 2) {
         const size_t bytes = sizeof(double) * ctx->n_cells;
         HIP_TRY(ctx, hipMemcpyAsync(h, ctx->pp_h, bytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -631,6 +697,29 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
                                     hipMemcpyDeviceToDevice, ctx->stream));
     }
     ctx->last_amax_slot = n_steps % 3;
+    return DSVE_OK;
+}
+
+dsve_status dsve_prepare_run(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                             double *t_dev)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (!h || !q || !z || !t_dev) return fail(ctx, DSVE_E_ARG, "null pointer");
+    if (n_steps < 0) return fail(ctx, DSVE_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0 || (ctx->resident_ok && ctx->resident_mode == 0)) return DSVE_OK;
+    dsve_status st = build_tile_table(ctx, ctx->tile);
+    if (st != DSVE_OK || ctx->graph_steps == 0) return st;
+    return ensure_graphs(ctx, h, q, z, t_dev, n_steps);
+}
+
+dsve_status dsve_get_last_run(const dsve_ctx *ctx, int *graph_launches, int *graph_steps,
+                              int *direct_launches)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (graph_launches) *graph_launches = ctx->last_graph_launches;
+    if (graph_steps) *graph_steps = ctx->last_graph_steps;
+    if (direct_launches) *direct_launches = ctx->last_direct;
     return DSVE_OK;
 }
 
@@ -656,7 +745,13 @@ dsve_status dsve_sync(dsve_ctx *ctx)
     if (ctx->sticky != DSVE_OK) return ctx->sticky;
     unsigned int flags[4];
     HIP_TRY(ctx, hipMemcpy(flags, ctx->d_flags, sizeof flags, hipMemcpyDeviceToHost));
-    if (flags[0]) return fail(ctx, DSVE_E_NONHYPERBOLIC, "complex eigenvalues (arccos argument out of range)");
+    if (flags[0] & kFlagNonfinite)
+        return fail(ctx, DSVE_E_NONFINITE, "non-finite cubic parameters (an overflowed or NaN state)");
+    if (flags[0] & kFlagComplex)
+        return fail(ctx, DSVE_E_NONHYPERBOLIC, "complex eigenvalues (arccos argument out of range)");
+    if (flags[0] & kFlagCoalesce)
+        return fail(ctx, DSVE_E_NONHYPERBOLIC,
+                    "coalescing eigenvalues at a quadrature node (arccos argument +-1: R^-1 undefined)");
     if (ctx->last_amax_slot >= 0) {
         const int64_t C = ctx->n_channels;
         std::vector<unsigned long long> am(ctx->amax_slot);

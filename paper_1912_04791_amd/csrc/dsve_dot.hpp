@@ -258,11 +258,11 @@ __device__ __forceinline__ void flux_matrix(double h, double q, double g, const 
 
 // Largest |lambda| of a state by the numerical route (eigenvalues of the Schur form).
 template <int CL>
-__device__ __forceinline__ double speed_dot(double h, double q, double g, const Closure &K, bool &bad)
+__device__ __forceinline__ double speed_dot(double h, double q, double g, const Closure &K, unsigned &bad)
 {
     double A[3][3], Q[3][3];
     flux_matrix<CL>(h, q, g, K, A);
-    bad |= !schur3(A, Q);
+    bad |= schur3(A, Q) ? 0u : kFlagComplex;
     return fmax(fmax(fabs(A[0][0]), fabs(A[1][1])), fabs(A[2][2]));
 }
 
@@ -270,7 +270,7 @@ __device__ __forceinline__ double speed_dot(double h, double q, double g, const 
 template <int G, int CL>
 __device__ __forceinline__ void fluct_dot(double hL, double qL, double zL, double hR, double qR,
                                           double zR, double g, const Closure &K, double Dm[3],
-                                          double Dp[3], bool &bad)
+                                          double Dp[3], unsigned &bad)
 {
     const double dW[3] = {hR - hL, qR - qL, zR - zL};
     double SA[3] = {0.0, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
@@ -278,7 +278,7 @@ __device__ __forceinline__ void fluct_dot(double hL, double qL, double zL, doubl
         const double s = Gauss<G>::s[k], w = Gauss<G>::w[k];
         double A[3][3], lam[3], R[3][3], Ri[3][3];
         flux_matrix<CL>(fma(s, dW[0], hL), fma(s, dW[1], qL), g, K, A);
-        bad |= !eig3_numeric(A, lam, R);
+        bad |= eig3_numeric(A, lam, R) ? 0u : kFlagComplex;
         inverse3_lu(R, Ri);
         // |A| = R |Lambda| R^-1 (Eq. asbA), then the node's contributions to sum_k w_k (A, |A|) dW
 #pragma unroll

@@ -17,7 +17,7 @@
 //              instead of queueing on one (S = 1, 2 or 4, a launch parameter).
 //   clocks     float64 [C] twice (the caller's array and the context's copy): step n reads one
 //              and writes t + dt to the other, so every thread sees the step's start time
-//   flags      uint32 [4]: [0] non-hyperbolic state seen
+//   flags      uint32 [4]: [0] deferred error bits (kFlag*) of the states and nodes seen
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +38,12 @@ enum { LAW_GRASS = 0, LAW_GRASS_THR = 1, LAW_POWER = 2, LAW_MPM = 3, LAW_VANRIJN
 // (then |u|^(beta - 1) is a short product instead of a general power).
 enum { CL_GRASS = LAW_GRASS, CL_GRASS_THR = LAW_GRASS_THR, CL_POWER = LAW_POWER, CL_MPM = LAW_MPM,
        CL_VANRIJN = LAW_VANRIJN, CL_POWER_INT = 5, kNumClosures = 6 };
+
+// Deferred device error bits, or-ed into flags[0] and read back by dsve_sync.
+constexpr unsigned kFlagComplex = 1u;    // complex eigenvalues: arccos argument past 1 + tol, or k1 <= 0
+constexpr unsigned kFlagCoalesce = 2u;   // a quadrature node whose arccos argument is +-1 to working
+                                         // precision: two eigenvalues equal, R^-1 does not exist
+constexpr unsigned kFlagNonfinite = 4u;  // a non-finite arccos argument (an overflowed or NaN state)
 
 constexpr int kMaxGauss = 5;
 constexpr int kMaxTile = 256;     // threads (= edges) per workgroup of the step kernel, at most

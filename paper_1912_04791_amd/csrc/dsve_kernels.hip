@@ -106,16 +106,16 @@ __device__ __forceinline__ double amax_of(const unsigned long long *__restrict__
     return m;
 }
 
-__device__ __forceinline__ void raise_flag(unsigned int *flags, bool bad)
+__device__ __forceinline__ void raise_flag(unsigned int *flags, unsigned bad)
 {
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1u);
+    if (bad) atomicOr(&flags[0], bad);
 }
 
 // Edge fluctuation and cell speed for the chosen precision and closure form.
 template <int G, int PREC, int CL>
 __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, double hR, double qR,
                                            double zR, double g, const Closure &K, double Dm[3],
-                                           double Dp[3], bool &bad)
+                                           double Dp[3], unsigned &bad)
 {
     if constexpr (PREC == PREC_FP64) fluct64<G, CL>(hL, qL, zL, hR, qR, zR, g, K, Dm, Dp, bad);
     else if constexpr (PREC == PREC_MIXED) fluct_mixed<G, CL>(hL, qL, zL, hR, qR, zR, g, K, Dm, Dp, bad);
@@ -124,7 +124,7 @@ __device__ __forceinline__ void edge_fluct(double hL, double qL, double zL, doub
 
 template <int PREC, int CL>
 __device__ __forceinline__ double cell_speed(double h, double q, double g, const Closure &K,
-                                             bool &bad)
+                                             unsigned &bad)
 {
     if constexpr (PREC == PREC_FP64) return speed64<CL>(h, q, g, K, bad);
     else if constexpr (PREC == PREC_MIXED) return speed_mixed<CL>(h, q, g, K, bad);
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         if (c != home) ci = CH[c];
         const Closure K = closure_of(ci);
         const Idx e = ge - eoc;
-        bool bad = false;
+        unsigned bad = 0u;
         double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
         double hR = 0.0, qR = 0.0, zR = 0.0;
         double hL = 0.0, qL = 0.0, zL = 0.0;
@@ -340,7 +340,7 @@ void k_resident(ResidentArgs A)
     __shared__ double s_dm[3][NT + 1];    // D^- of the edges
     __shared__ unsigned long long s_w[NT / 64];
     const int t = threadIdx.x;
-    bool bad = false;
+    unsigned bad = 0u;
     for (int c = blockIdx.x; c < A.n_channels; c += gridDim.x) {
         const ChanInfo ci = A.ch[c];
         const Closure K = closure_of(ci);
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(CflArgs A)
     int c = home;                  // channel of this lane's cell
     int cur = home;                // the wave's current channel
     unsigned long long acc = 0ull; // this lane's maximum over its cells in `cur`
-    bool bad = false;
+    unsigned bad = 0u;
     for (int64_t i0 = start; i0 < end; i0 += kCflThreads) {
         const int64_t i = i0 + threadIdx.x;
         const bool active = i < end;
@@ -494,7 +494,7 @@ template <int G, int PREC, int CL>
 __global__ __launch_bounds__(256) void k_fluct(FluctArgs A)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
+    unsigned bad = 0u;
     if (e < A.n) {
         double Dm[3], Dp[3];
         edge_fluct<G, PREC, CL>(A.hL[e], A.qL[e], A.zL[e], A.hR[e], A.qR[e], A.zR[e], A.g, closure_of(A.ci),

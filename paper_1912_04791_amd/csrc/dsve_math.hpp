@@ -283,9 +283,13 @@ struct Eig64 {
     double inv_gp;          // 1 / (g21 g31 g32)
 };
 
+// Error bits (kFlag*) go to `bad`: complex roots; a non-finite arccos argument; and an argument
+// of +-1 after the clamp, where two roots coalesce to working precision (sin(phi) = 0, so the
+// gap product and R^-1 do not exist).  Callers that need only the eigenvalues (the CFL speed)
+// drop the last bit.
 template <int CL>
 __device__ __forceinline__ void eig64(double h, double q, double g, const Closure &K, Eig64 &E,
-                                      bool &bad)
+                                      unsigned &bad)
 {
     const double gh = g * h;
     const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
@@ -296,10 +300,12 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     const double r1 = rsqrt_h(k1);
     const double r13 = r1 * r1 * r1;
     double x = (0.5 * k2) * r13;   // k2 / sqrt(4 k1^3)
-    // complex roots: arccos argument beyond 1 + tol or k1 <= 0 (NaN compares false: a NaN
-    // state is reported as non-finite by the CFL maximum instead)
-    bad |= (fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0);
-    x = fmin(fmax(x, -1.0), 1.0);   // a NaN x only arises with a NaN Fr, which the roots carry
+    // complex roots: arccos argument beyond 1 + tol or k1 <= 0; a NaN argument (an overflowed
+    // or NaN state: fmax below would turn it into -1) is reported as non-finite
+    bad |= ((fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0)) ? kFlagComplex : 0u;
+    bad |= (x != x) ? kFlagNonfinite : 0u;
+    x = fmin(fmax(x, -1.0), 1.0);
+    bad |= (fabs(x) == 1.0) ? kFlagCoalesce : 0u;
     double cs, sn, inv_y;
     trisect(x, cs, sn, inv_y);
     const double m = (2.0 / 3.0) * (k1 * r1);
@@ -321,14 +327,17 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
 
 // Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).
 template <int CL>
-__device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, bool &bad)
+__device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, unsigned &bad)
 {
     Eig64 E;
-    eig64<CL>(h, q, g, K, E, bad);
+    unsigned eb = 0u;
+    eig64<CL>(h, q, g, K, E, eb);
+    bad |= eb & ~kFlagCoalesce;   // coalescing roots still have well-defined speeds
     return E.c * fmax(fmax(fabs(E.mu1), fabs(E.mu2)), fabs(E.mu3));
 }
 
-// Accumulate one quadrature node: SA += w A dW, SB += w |A| dW.
+// Accumulate one quadrature node: SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node,
+// and the weights sum to one, so the caller takes sum_k w_k dq = dq), SB += w |A| dW.
 __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, double dh, double dq,
                                                   double dz, double SA[3], double SB[3])
 {
@@ -353,7 +362,6 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
     const double B1 = fma(b1, mu1, fma(b2, mu2, b3 * mu3));
     const double B2 = fma(b1, fma(e1, e1, -1.0), fma(b2, fma(e2, e2, -1.0), b3 * fma(e3, e3, -1.0)));
     const double wc = w * c;
-    SA[0] = fma(w, dq, SA[0]);
     SA[1] = fma(wc * c, A1n, SA[1]);
     SA[2] = fma(wc, A2n, SA[2]);
     SB[0] = fma(c, B0, SB[0]);
@@ -365,10 +373,10 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
 template <int G, int CL>
 __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double hR, double qR,
                                         double zR, double g, const Closure &K, double Dm[3],
-                                        double Dp[3], bool &bad)
+                                        double Dp[3], unsigned &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
-    double SA[3] = {0.0, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
+    double SA[3] = {dq, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const double s = Gauss<G>::s[k];
@@ -386,7 +394,9 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 // ---------------------------------------------------------------------------
 // Mixed form: FP32 eigenstructure and quadrature; a node whose arccos argument lies within
 // kMixedFp64Band of +-1 (coalescing eigenvalues: Fr near +-1 with weak transport) is redone
-// in FP64 from the FP64 path state.  The jumps dW are formed in FP64 and rounded once.
+// in FP64 from the FP64 path state.  The jumps dW and the free-surface jump dh + dz are formed
+// in FP64 and rounded once; the h-row of sum_k w_k A dW is dq in FP64, so the water mass the
+// update moves between cells telescopes to FP64 rounding.
 struct EigF {
     float Fr, c, inv_c, b, kFr;
     float mu1, mu2, mu3;
@@ -426,18 +436,20 @@ __device__ __forceinline__ bool eigf(float h, float q, float g, const Closure &K
     return true;
 }
 
-__device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float dh, float dq, float dz,
+// One FP32 node: SA += w A dW (rows 1, 2), SB += w |A| dW.  eta = dh + dz (rounded from FP64):
+// (1 - Fr^2) dh + dz = eta - Fr^2 dh keeps a still free surface (eta = 0, Fr = 0) exact.
+__device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float dh, float dq, float eta,
                                                  float SA[3], float SB[3])
 {
     const float Fr = E.Fr, c = E.c;
     const float mu1 = E.mu1, mu2 = E.mu2, mu3 = E.mu3;
     const float dqn = dq * E.inv_c;
-    const float base = fmaf(-Fr, Fr, 1.0f);
-    const float A1n = fmaf(base, dh, fmaf(2.0f * Fr, dqn, dz));
+    const float nF2 = -Fr * Fr;
+    const float A1n = fmaf(nF2, dh, fmaf(2.0f * Fr, dqn, eta));
     const float A2n = E.b * fmaf(-E.kFr, dh, dqn);
-    const float n1 = fmaf(fmaf(mu2, mu3, base), dh, fmaf(mu1, dqn, dz));
-    const float n2 = fmaf(fmaf(mu3, mu1, base), dh, fmaf(mu2, dqn, dz));
-    const float n3 = fmaf(fmaf(mu1, mu2, base), dh, fmaf(mu3, dqn, dz));
+    const float n1 = fmaf(fmaf(mu2, mu3, nF2), dh, fmaf(mu1, dqn, eta));
+    const float n2 = fmaf(fmaf(mu3, mu1, nF2), dh, fmaf(mu2, dqn, eta));
+    const float n3 = fmaf(fmaf(mu1, mu2, nF2), dh, fmaf(mu3, dqn, eta));
     const float wP = w * __builtin_amdgcn_rcpf(E.g21 * E.g31 * E.g32);
     const float b1 = n1 * (fabsf(mu1) * E.g32) * wP;
     const float b2 = -n2 * (fabsf(mu2) * E.g31) * wP;
@@ -447,7 +459,6 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
     const float B1 = fmaf(b1, mu1, fmaf(b2, mu2, b3 * mu3));
     const float B2 = fmaf(b1, fmaf(e1, e1, -1.0f), fmaf(b2, fmaf(e2, e2, -1.0f), b3 * fmaf(e3, e3, -1.0f)));
     const float wc = w * c;
-    SA[0] = fmaf(w, dq, SA[0]);
     SA[1] = fmaf(wc * c, A1n, SA[1]);
     SA[2] = fmaf(wc, A2n, SA[2]);
     SB[0] = fmaf(c, B0, SB[0]);
@@ -458,20 +469,20 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
 template <int G, int CL>
 __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, double hR, double qR,
                                             double zR, double g, const Closure &K, double Dm[3],
-                                            double Dp[3], bool &bad)
+                                            double Dp[3], unsigned &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
-    const float dhf = (float)dh, dqf = (float)dq, dzf = (float)dz;
+    const float dhf = (float)dh, dqf = (float)dq, etaf = (float)(dh + dz);
     const float hLf = (float)hL, qLf = (float)qL;
     const float gf = (float)g;
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
-    double SA64[3] = {0.0, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
+    double SA64[3] = {dq, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const float sf = (float)Gauss<G>::s[k];
         EigF E;
         if (eigf<CL>(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, K, E)) {
-            node_accumulatef(E, (float)Gauss<G>::w[k], dhf, dqf, dzf, SA, SB);
+            node_accumulatef(E, (float)Gauss<G>::w[k], dhf, dqf, etaf, SA, SB);
         } else {
             const double s = Gauss<G>::s[k];
             Eig64 E64;
@@ -489,7 +500,7 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
 
 template <int CL>
 __device__ __forceinline__ double speed_mixed(double h, double q, double g, const Closure &K,
-                                              bool &bad)
+                                              unsigned &bad)
 {
     EigF E;
     if (eigf<CL>((float)h, (float)q, (float)g, K, E))

@@ -122,14 +122,17 @@ lib.dsve_set_resident.argtypes = [_ctxp, ctypes.c_int]
 lib.dsve_get_resident.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int)]
 lib.dsve_device_cus.argtypes = [_ctxp]
 lib.dsve_device_cus.restype = ctypes.c_int
-assert lib.dsve_abi_version() == 4, "libdsve ABI version mismatch"
+lib.dsve_prepare_run.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, _vp]
+lib.dsve_get_last_run.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)]
+assert lib.dsve_abi_version() == 5, "libdsve ABI version mismatch"
 
 ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destroy",
                 "dot_edge_fluct", "cell_update", "cfl_reduce", "adot_step", "adot_step_batched",
                 "dsve_sync", "dsve_last_error", "dsve_clear_error", "dsve_set_launch",
                 "dsve_get_launch", "dsve_set_cfl_split", "dsve_get_cfl_split", "dsve_set_resident",
-                "dsve_get_resident", "dsve_autotune",
-                "dsve_device_cus")
+                "dsve_get_resident", "dsve_autotune", "dsve_device_cus", "dsve_prepare_run",
+                "dsve_get_last_run")
 
 
 class DsveError(RuntimeError):
@@ -323,6 +326,19 @@ class Context:
         fn = lib.adot_step_batched if self.batched else lib.adot_step
         self._check(fn(self._h, *self._state(h, q, z), int(n_steps),
                        _ptr(t, self.n_channels, device=self.device)), "adot_step")
+
+    def prepare_run(self, h, q, z, n_steps: int, t):
+        """Capture the graphs a run of n_steps on these tensors replays (no work enqueued)."""
+        self._check(lib.dsve_prepare_run(self._h, *self._state(h, q, z), int(n_steps),
+                                         _ptr(t, self.n_channels, device=self.device)),
+                    "dsve_prepare_run")
+
+    def last_run(self):
+        """(graph replays, steps they ran, kernels launched directly) of the last run."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(lib.dsve_get_last_run(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                    "dsve_get_last_run")
+        return a.value, b.value, c.value
 
     def sync(self):
         self._check(lib.dsve_sync(self._h), "dsve_sync")

@@ -188,6 +188,19 @@ def make_c1(n_cells: int = 250, steps: int = 200) -> Workload:
                    0.0, steps, meta={"L": L})
 
 
+def make_riemann(n_cells: int, length: float, x_jump: float, left: dict, right: dict,
+                 A_g: float, porosity: float, steps: int = 0) -> Workload:
+    """Riemann problem on [0, length] with the jump at x_jump: conservative states
+    ``{"h", "q", "z"}`` left and right, transmissive ends (the set-up of Sec. 4.1)."""
+    x = cell_centres(n_cells, length)
+    lm = x < x_jump
+    h = np.where(lm, left["h"], right["h"])
+    q = np.where(lm, left["q"], right["q"])
+    z = np.where(lm, left["z"], right["z"])
+    return _single("riemann", h, q, z, length / n_cells, A_g, porosity, BC_TRANSMISSIVE,
+                   BC_TRANSMISSIVE, 0.0, steps, meta={"L": length, "x_jump": x_jump})
+
+
 def _fourier_noise(coefs: np.ndarray, n: int) -> np.ndarray:
     """Rows of sum_{m=0..M} Re(c_m exp(2 pi i m x)), x = (j + 1/2)/n, each rescaled to unit
     standard deviation: periodic Gaussian noise limited to Fourier modes m <= M."""

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     lib.dsve_abi_version.restype = ctypes.c_int
-    assert lib.dsve_abi_version() == 4
+    assert lib.dsve_abi_version() == 5
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdsve.so not built")

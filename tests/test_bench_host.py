@@ -17,38 +17,110 @@ def test_code_only_drops_comments_and_whitespace_but_keeps_strings():
     assert bench._code_only("int a = 1;") != bench._code_only("int a = 2;")
 
 
-def test_traffic_is_used_only_for_the_current_code(tmp_path, monkeypatch):
+def _write_profiles(tmp_path, monkeypatch, entries, h="h"):
     prof = tmp_path / "profiles"
-    prof.mkdir()
-    ok = {"kernel_hash": bench.kernel_source_hash(), "bytes_per_launch": 1.0e6}
-    stale = {"kernel_hash": "0" * 16, "bytes_per_launch": 2.0e6}
-    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ok, "c2:mixed": stale}))
+    prof.mkdir(exist_ok=True)
+    (prof / "traffic.json").write_text(json.dumps(entries))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # the hash itself reads the sources under the real root
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: ok["kernel_hash"])
-    assert bench.measured_traffic("c2", "fp64") == 1.0e6
-    assert bench.measured_traffic("c2", "mixed") is None
-    assert bench.measured_traffic("c3", "fp64") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+
+
+def test_counter_figures_only_for_the_current_code_and_launch(tmp_path, monkeypatch):
+    ok = {"kernel_hash": "h", "launch": [256, 12, 1], "bytes_per_launch": 1.0e6}
+    stale = {"kernel_hash": "0" * 16, "launch": [256, 12, 1], "bytes_per_launch": 2.0e6}
+    _write_profiles(tmp_path, monkeypatch, {"c2:fp64": ok, "c2:mixed": stale})
+    launch = (256, 12, 60, 1)   # tile, blocks per CU, graph steps, CFL sub-slots
+    assert bench.counter_figures("c2", "fp64", 2 ** 20, 0.03, launch)["traffic"] == 1.0e6
+    assert bench.counter_figures("c2", "mixed", 2 ** 20, 0.03, launch)["traffic"] is None
+    assert bench.counter_figures("c3", "fp64", 2 ** 20, 0.03, launch)["traffic"] is None
+    # taken at another launch: not used
+    other = (256, 24, 60, 1)
+    assert bench.counter_figures("c2", "fp64", 2 ** 20, 0.03, other)["traffic"] is None
 
 
 def test_valu_issue_share_from_the_counter_summary(tmp_path, monkeypatch):
-    prof = tmp_path / "profiles"
-    prof.mkdir()
     ent = {"kernel_hash": "h", "valu_insts_per_edge": 640.0}
-    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ent}))
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h")
+    _write_profiles(tmp_path, monkeypatch, {"c2:fp64": ent})
     # 640 instructions per edge, 2^20 edges: 2^14 waves x 640 x 4 cycles / 1024 SIMDs / 2.4 GHz
     busy = 2 ** 14 * 640 * 4 / 1024 / 2.4e9
-    v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
+    v = bench.counter_figures("c2", "fp64", 2 ** 20, busy * 2 * 1e3, None)["valu_issue"]
     assert v["insts_per_edge"] == 640.0 and abs(v["frac"] - 0.5) < 1e-12
     assert "active_frac" not in v
-    assert bench.valu_issue("c3", "fp64", 2 ** 20, 1.0) is None
+    assert bench.counter_figures("c3", "fp64", 2 ** 20, 1.0, None)["valu_issue"] is None
     # with the VALU-active counter: 704 four-cycle units per edge is 1.1 times the issue time
     ent["valu_active_per_edge"] = 704.0
-    (prof / "traffic.json").write_text(json.dumps({"c2:fp64": ent}))
-    v = bench.valu_issue("c2", "fp64", 2 ** 20, busy * 2 * 1e3)
+    _write_profiles(tmp_path, monkeypatch, {"c2:fp64": ent})
+    v = bench.counter_figures("c2", "fp64", 2 ** 20, busy * 2 * 1e3, None)["valu_issue"]
     assert abs(v["active_frac"] - 0.55) < 1e-12 and v["active_per_edge"] == 704.0
+
+
+def test_counter_flop_rate_and_fraction(tmp_path, monkeypatch):
+    ent = {"kernel_hash": "h", "flops_f64": 7.0e11, "flops_f32": 0.86e11}
+    _write_profiles(tmp_path, monkeypatch, {"c5:fp64": ent, "c5:mixed": ent})
+    cf = bench.counter_figures("c5", "fp64", 10 ** 8, 10.0, None)["counter_flops"]
+    assert abs(cf["tflops"] - 78.6) < 1e-9 and abs(cf["frac"] - 1.0) < 1e-12
+    assert abs(cf["per_edge_update"] - 7860.0) < 1e-9
+    # the mixed form against the rate non-packed FP32 can issue (the FP64 rate)
+    cm = bench.counter_figures("c5", "mixed", 10 ** 8, 20.0, None)["counter_flops"]
+    assert cm["peak"] == 78.6 and abs(cm["frac"] - 0.5) < 1e-12
+
+
+def test_valu_flops_counts_an_fma_twice():
+    from paper_1912_04791_amd import profsum
+    c = {"SQ_INSTS_VALU_ADD_F64": [1.0], "SQ_INSTS_VALU_MUL_F64": [2.0],
+         "SQ_INSTS_VALU_FMA_F64": [3.0, 3.0, 5.0], "SQ_INSTS_VALU_TRANS_F64": [4.0],
+         "SQ_INSTS_VALU_FMA_F32": [10.0]}
+    f64, f32 = profsum.valu_flops(c)
+    assert f64 == 64.0 * (1 + 2 + 2 * 3 + 4) and f32 == 64.0 * 20
+
+
+def test_trace_runs_match_the_logged_runs(tmp_path):
+    from paper_1912_04791_amd import profsum
+    hdr = "Kind,Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"
+    rows, t, d = [], 0, 0
+
+    def disp(name, dur):
+        nonlocal t, d
+        d += 1
+        rows.append(f'KERNEL_DISPATCH,{d},"{name}",{t},{t + dur}')
+        t += dur + 5
+
+    s64, s32 = "dsve::k_step<3, 0, 0, false>(a)", "dsve::k_step<3, 1, 0, false>(a)"
+    for name, n, dur in ((s64, 2, 100), (s64, 3, 90), (s32, 2, 70), (s32, 3, 60), (s64, 4, 95)):
+        disp("dsve::k_fill_u64(x)", 1)
+        disp("dsve::k_cfl<0, 0>(a)", 10)
+        for _ in range(n):
+            disp(name, dur)
+    disp("dsve::k_cfl<0, 0>(a)", 10)   # a cfl_reduce call: no step kernels, no run
+    (tmp_path / "run_kernel_trace.csv").write_text("\n".join([hdr] + rows) + "\n")
+    log = tmp_path / "bench.err"
+    log.write_text("\n".join([
+        "[run] workload=c5 precision=fp64 solver=adot steps=2 kind=warmup",
+        "[run] workload=c5 precision=fp64 solver=adot steps=3 kind=timed",
+        "[bench] c5 fp64: ...",
+        "[run] workload=c5 precision=mixed solver=adot steps=2 kind=warmup",
+        "[run] workload=c5 precision=mixed solver=adot steps=3 kind=timed",
+        "[run] workload=c5 precision=fp64 solver=adot steps=4 kind=full"]) + "\n")
+    pairs = profsum.match_runs(profsum.read_runs(str(log)), profsum.trace_runs(str(tmp_path)))
+    timed64 = [tr for lg, tr in pairs if lg["kind"] == "timed" and lg["precision"] == "fp64"]
+    assert len(timed64) == 1 and timed64[0][1] == [90, 90, 90]
+    st = profsum.dispatch_stats(timed64[0][1])
+    assert st["n"] == 3 and abs(st["mean_us"] - 0.09) < 1e-12
+    full = [tr for lg, tr in pairs if lg["kind"] == "full"]
+    assert full[0][1] == [95] * 4
+    # a missing log line is an error, not a silent mismatch
+    import pytest
+    with pytest.raises(ValueError):
+        profsum.match_runs(profsum.read_runs(str(log))[1:], profsum.trace_runs(str(tmp_path)))
+
+
+def test_host_cpu_threads_follow_the_cpu_share(monkeypatch):
+    monkeypatch.setenv("OMP_NUM_THREADS", "3")
+    c = bench.host_cpu()
+    assert c["threads"] == min(3, c["affinity"]) and c["nproc"] >= c["affinity"] >= 1
+    monkeypatch.delenv("OMP_NUM_THREADS")
+    assert bench.host_cpu()["threads"] == bench.host_cpu()["affinity"]
 
 
 def test_profile_calibration_is_the_first_copy(tmp_path):
@@ -91,6 +163,5 @@ def test_alu_roofline_peaks():
 
 def test_profile_timing_note_wording():
     from paper_1912_04791_amd import profsum
-    assert "is higher" in profsum.timing_note("26.5-28.5", 33.4)
-    assert "agrees with it within 2%" in profsum.timing_note("398", 399.5)
-    assert "agrees with it within 2%" in profsum.timing_note("415", 412.4)
+    assert "below it" in profsum.timing_note(3500.0, 3400.0)
+    assert "above it" in profsum.timing_note(27.0, 29.0)

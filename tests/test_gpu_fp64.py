@@ -64,13 +64,17 @@ def test_pairwise_fluct_matches_oracle(torch_dev, dsve, G):
     ctx.sync()
     rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / (1.0 - xi_p), Ag, G=G)
     gm, gp = Dm.cpu().numpy(), Dp.cpu().numpy()
+    # per edge, relative to the edge's own fluctuation size: every edge within the FP64 bar (the
+    # oracle and an exact-arithmetic evaluation of the kernels' matrix-vector form agree to 3e-14
+    # per edge on these inputs)
+    sc = np.abs(rm).max(axis=0) + np.abs(rp).max(axis=0)
     for got, ref in ((gm, rm), (gp, rp)):
         l1 = np.abs(got - ref).sum() / np.abs(ref).sum()
         assert l1 <= TOL, l1
-        # per edge, relative to the edge's own fluctuation size
-        sc = np.abs(rm).max(axis=0) + np.abs(rp).max(axis=0)
         per = np.abs(got - ref).max(axis=0) / sc
-        assert np.quantile(per, 0.999) <= 1e-12 and per.max() <= 1e-8, (per.max(), np.argmax(per))
+        print(f"G={G}: per-edge relative error max {per.max():.3g} (edge {np.argmax(per)}), "
+              f"99.9% {np.quantile(per, 0.999):.3g}, L1 {l1:.3g}")
+        assert per.max() <= TOL, (per.max(), np.argmax(per))
     ctx.close()
 
 
@@ -376,4 +380,63 @@ def test_runs_write_only_the_callers_arrays(torch_dev, dsve, resident):
     ref = oracle_run(wl)
     assert per_channel_rel_l1(got, ref, wl.offsets).max() <= TOL
     np.testing.assert_allclose(got[3], ref[3], rtol=1e-13)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coalescing_roots_are_reported(torch_dev, dsve, precision):
+    # a fixed bed at Fr = 1 (g = 4, h = 1, q = 2: every quantity exact, arccos argument 1): two
+    # roots coincide and R^-1 does not exist; the oracle reports the same edges (its pins)
+    torch = torch_dev
+    n = 100
+    f64 = dict(dtype=torch.float64, device="cuda")
+    ctx = dsve.Context.single(16, g=4.0, porosity=0.0, A_g=0.0, dx=1.0, precision=precision)
+    one, two = torch.ones(n, **f64), torch.full((n,), 2.0, **f64)
+    Dm, Dp = torch.zeros(3, n, **f64), torch.zeros(3, n, **f64)
+    ctx.dot_edge_fluct(one, two, torch.zeros(n, **f64), one, two, torch.full((n,), 0.1, **f64), Dm, Dp)
+    assert ctx.sync_status() == dsve.E_NONHYPERBOLIC
+    assert "coalescing" in ctx.last_error()
+    ctx.close()
+    # a movable bed at the same states: no error
+    ctx = dsve.Context.single(16, g=4.0, porosity=0.0, A_g=0.01, dx=1.0, precision=precision)
+    ctx.dot_edge_fluct(one, two, torch.zeros(n, **f64), one, two, torch.full((n,), 0.1, **f64), Dm, Dp)
+    ctx.sync()
+    assert torch.all(torch.isfinite(Dm)) and torch.all(torch.isfinite(Dp))
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fixed_bed_next_to_coalescence_is_reported_or_bounded(torch_dev, dsve, precision):
+    # Fr = 1 +- 1e-9 over a fixed bed: the roots differ by 1e-9 c, below what the arccos argument
+    # resolves; each edge is either reported (roots equal to working precision) or finite and
+    # bounded by the size of its jump (|D| <= |A| |dW| ~ c^2 |dz|), never huge numbers
+    torch = torch_dev
+    n = 64
+    f64 = dict(dtype=torch.float64, device="cuda")
+    q = torch.tensor([2.0 * (1.0 + (1e-9 if k % 2 else -1e-9)) for k in range(n)], **f64)
+    one = torch.ones(n, **f64)
+    Dm, Dp = torch.zeros(3, n, **f64), torch.zeros(3, n, **f64)
+    ctx = dsve.Context.single(16, g=4.0, porosity=0.0, A_g=0.0, dx=1.0, precision=precision)
+    ctx.dot_edge_fluct(one, q, torch.zeros(n, **f64), one, q, torch.full((n,), 0.1, **f64), Dm, Dp)
+    st = ctx.sync_status()
+    if st == dsve.OK:
+        assert torch.all(torch.isfinite(Dm)) and torch.all(torch.isfinite(Dp))
+        assert float(torch.max(torch.abs(Dm))) < 10.0 and float(torch.max(torch.abs(Dp))) < 10.0
+    else:
+        assert st == dsve.E_NONHYPERBOLIC
+    ctx.close()
+
+
+def test_overflowed_state_is_reported_as_nonfinite(torch_dev, dsve):
+    # g h^3 overflows: the arccos argument is NaN, which the clamp would otherwise turn into -1
+    torch = torch_dev
+    n = 64
+    f64 = dict(dtype=torch.float64, device="cuda")
+    h = torch.full((n,), 1e110, **f64)
+    Dm, Dp = torch.zeros(3, n, **f64), torch.zeros(3, n, **f64)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.01, dx=1.0)
+    ctx.dot_edge_fluct(h, h, torch.zeros(n, **f64), torch.ones(n, **f64), torch.ones(n, **f64),
+                       torch.zeros(n, **f64), Dm, Dp)
+    assert ctx.sync_status() == dsve.E_NONFINITE
     ctx.close()

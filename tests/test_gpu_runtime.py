@@ -269,3 +269,45 @@ def test_cfl_reduce_past_32_bit_cell_indices(torch_dev, dsve, where):
     fast = oracle.cfl_amax(np.array([2.0]), np.array([3.0]), np.array([0.0]), 9.81, xi, 0.01)
     assert fast > base
     assert abs(float(amax[0]) - fast) <= 1e-14 * fast
+
+
+@pytest.mark.parametrize("graph_steps,n", [(60, 5), (60, 20), (60, 59), (60, 60), (60, 61),
+                                           (60, 125), (6, 20), (6, 7)])
+def test_every_step_replays_a_graph(torch_dev, dsve, graph_steps, n):
+    # a run of n steps replays n // graph_steps full graphs and one graph of the remaining
+    # steps; bitwise the same as launching every step directly
+    wl = inputs.make_c4(n_channels=7, len_lo=600, len_hi=3000, steps=n)
+    outs = []
+    for gs in (graph_steps, 0):
+        ctx = dsve.Context.from_workload(wl)
+        ctx.set_launch(256, 2, gs)
+        h, q, z, t = dsve.upload(wl)
+        ctx.adot_step(h, q, z, n, t)
+        ctx.sync()
+        launches, gsteps, direct = ctx.last_run()
+        if gs:
+            assert (launches, gsteps, direct) == (n // gs + (1 if n % gs else 0), n, 0)
+        else:
+            assert (launches, gsteps, direct) == (0, 0, n)
+        outs.append(to_np(h, q, z, t))
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_prepared_run_replays_without_capture(torch_dev, dsve):
+    # graphs captured ahead for a run length are reused by that run; other lengths still run
+    wl = inputs.make_c2(n_cells=20_000, steps=23)
+    ctx = dsve.Context.from_workload(wl)
+    ctx.set_launch(256, 4, 12)
+    h, q, z, t = dsve.upload(wl)
+    ctx.prepare_run(h, q, z, 23, t)
+    ctx.adot_step(h, q, z, 23, t)
+    ctx.sync()
+    assert ctx.last_run() == (2, 23, 0)
+    ctx.adot_step(h, q, z, 5, t)
+    ctx.sync()
+    assert ctx.last_run() == (1, 5, 0)
+    ref = oracle_run(wl, steps=28)
+    assert max_rel_l1(to_np(h, q, z, t), ref) <= 1e-12
+    ctx.close()

@@ -180,3 +180,38 @@ def test_complex_roots_are_reported(orc, h, u, Ag):
     assert np.max(np.abs(np.linalg.eigvals(A).imag)) > 0.1
     e = orc.eigensystem([h], [h * u], [0.0], G, 1.0, Ag, check=False)
     assert e["status"] == orc.E_NONHYPERBOLIC
+
+
+def test_coalescing_roots_of_a_fixed_bed_are_reported(orc):
+    # a fixed bed (A_g = 0) at Fr = 1: the roots u - c and 0 coincide and A is defective (one
+    # eigenvector for the double root), so R^-1 of Eq. RR-1 does not exist.  With g = 4, h = 1
+    # and q = 2 every quantity is exact: Fr = 1, k1 = 4, k2 = 16, arccos argument 1.
+    A = dot_numeric.flux_matrix(1.0, 2.0, 4.0, 1.0, 0.0)
+    lam = np.sort(np.linalg.eigvals(A).real)
+    assert abs(lam[0]) < 1e-7 and abs(lam[1]) < 1e-7 and abs(lam[2] - 4.0) < 1e-12
+    e = orc.eigensystem([1.0], [2.0], [0.0], 4.0, 1.0, 0.0, check=False)
+    assert e["status"] == orc.E_NONHYPERBOLIC
+    assert e["lam"][0][0] == e["lam"][0][1] and abs(e["lam"][0][0]) < 1e-15
+    # the edge whose quadrature nodes all sit there is reported too, not returned as numbers
+    Dm, Dp = orc.fluct(([1.0], [2.0], [0.0]), ([1.0], [2.0], [0.1]), 4.0, 1.0, 0.0, check=False)
+    with pytest.raises(orc.OracleError) as ex:
+        orc.fluct(([1.0], [2.0], [0.0]), ([1.0], [2.0], [0.1]), 4.0, 1.0, 0.0)
+    assert ex.value.status == orc.E_NONHYPERBOLIC
+    # the CFL speed needs no R^-1: the state's largest speed u + c = 4 is reported
+    assert orc.cfl_amax([1.0], [2.0], [0.0], 4.0, 1.0, 0.0) == 4.0
+    # a movable bed at the same state keeps its roots apart (Sec. 3.3)
+    e = orc.eigensystem([1.0], [2.0], [0.0], 4.0, 1.0, 0.01, check=False)
+    assert e["status"] == orc.OK and e["lam"][0][1] - e["lam"][0][0] > 0.1
+
+
+@pytest.mark.parametrize("dfr", [1e-9, -1e-9])
+def test_fixed_bed_next_to_coalescence(orc, dfr):
+    # Fr = 1 +- 1e-9 over a fixed bed: the roots are apart by 1e-9 c, below what the arccos
+    # argument resolves (1 - x ~ 3e-19), so they coincide in FP64 and the state is reported
+    q = 2.0 * (1.0 + dfr)
+    e = orc.eigensystem([1.0], [q], [0.0], 4.0, 1.0, 0.0, check=False)
+    lam = e["lam"][0]
+    if lam[0] == lam[1]:
+        assert e["status"] == orc.E_NONHYPERBOLIC
+    else:
+        assert e["status"] == orc.OK and np.all(np.isfinite(e["Rinv"]))
