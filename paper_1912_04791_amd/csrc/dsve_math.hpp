@@ -67,7 +67,7 @@ namespace dsve {
 constexpr double kSqrt3Half = 0.86602540378443864676372317075293618;
 constexpr double kAcosTol = 1e-12;            // tolerance on |arccos argument| - 1 before flagging
 constexpr double kInvGapScale = 2.59807621135331594029116951225880855;   // 3 sqrt3 / 2
-constexpr float kMixedFp64Band = 1e-3f;       // mixed form: 1 - |x| below this -> FP64 node
+constexpr float kMixedFp64Band = 1e-2f;       // mixed form: 1 - |x| below this -> FP64 node
 
 // Unrolling of the quadrature-node loop (independent nodes interleave for ILP when unrolled;
 // a rolled loop needs fewer registers).
@@ -325,15 +325,65 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     E.inv_gp = (kInvGapScale * r13) * inv_y;
 }
 
-// Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).
+// cos(arccos(a) / 3) for a in [0, 1] in FP32: the function is analytic there (its branch point is
+// at a = -1); a polynomial of degree 7 in t = 1 - a, interpolated at the Chebyshev nodes of
+// [0, 1] in 50-digit arithmetic, meets it to about 1 ulp in FP32.
+__device__ __forceinline__ float cos_third_acos(float a)
+{
+    const float t = 1.0f - a;
+    float p = -0.0005426077404990792f;
+    p = fmaf(p, t, 0.0008754234877415001f);
+    p = fmaf(p, t, -0.0015220807399600744f);
+    p = fmaf(p, t, -0.0008192436653189361f);
+    p = fmaf(p, t, -0.004411802161484957f);
+    p = fmaf(p, t, -0.01644226536154747f);
+    p = fmaf(p, t, -0.11111201345920563f);
+    return fmaf(p, t, 1.0f);
+}
+// The same in FP64: C = cos(arccos(a) / 3) is the root in [cos(pi/6), 1] of the trisection cubic
+// f(C) = 4C^3 - 3C - a, whose derivative 12C^2 - 3 is at least 6 there.  From the FP32 estimate,
+// two Newton steps in FP64 dividing by the derivative taken once in FP32: each takes an error e to
+// about e * 1e-7 + e^2 (1e-7 -> 4e-14 -> FP64 rounding).  Its FP32 constants are instruction
+// literals, so nothing stays in registers between calls.
+__device__ __forceinline__ double cos_third_acos(double a)
+{
+    const float cf = cos_third_acos((float)a);
+    const double r = (double)__builtin_amdgcn_rcpf(fmaf(12.0f * cf, cf, -3.0f));
+    double c = (double)cf;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) c = fma(-fma(c, fma(4.0 * c, c, -3.0), -a), r, c);
+    return c;
+}
+
+// Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).  k1 is even
+// and k2 odd in Fr, so the spectrum at -Fr is the negation of the spectrum at Fr, and the largest
+// |mu| is the largest root at |Fr|: mu_3 = (2/3)(|Fr| + sqrt(k1) cos(theta')), theta' =
+// arccos(x')/3 with x' = x sign(Fr) the arccos argument at |Fr|.  For x' >= 0 (|Fr| below about 3
+// under weak transport) the cosine comes from the polynomial above; for x' < 0 from the
+// trisection of the fluctuation nodes.
 template <int CL>
 __device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, unsigned &bad)
 {
-    Eig64 E;
-    unsigned eb = 0u;
-    eig64<CL>(h, q, g, K, E, eb);
-    bad |= eb & ~kFlagCoalesce;   // coalescing roots still have well-defined speeds
-    return E.c * fmax(fmax(fabs(E.mu1), fabs(E.mu2)), fabs(E.mu3));
+    const double gh = g * h;
+    const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
+    const double Fr = q * t;
+    const double inv_c = h * t;
+    double k1, k2, b, kFr;
+    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
+    const double r1 = rsqrt_h(k1);
+    const double x = (0.5 * k2) * (r1 * r1 * r1);
+    bad |= ((fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0)) ? kFlagComplex : 0u;
+    bad |= (x != x) ? kFlagNonfinite : 0u;
+    const double xa = fmin(Fr < 0.0 ? -x : x, 1.0);
+    double cth;
+    if (xa >= 0.0) {
+        cth = cos_third_acos(xa);
+    } else {
+        double sn, inv_y;
+        trisect(fmax(xa, -1.0), cth, sn, inv_y);
+    }
+    // a NaN argument falls through both branches' arithmetic as NaN (the state is flagged)
+    return (gh * inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
 }
 
 // Accumulate one quadrature node: SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node,
@@ -498,13 +548,26 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     }
 }
 
+// CFL speed in FP32 for the mixed form (the largest root at |Fr|, as speed64); the FP64 speed
+// where the FP32 argument at |Fr| is negative, or within kMixedFp64Band of 1 as for the nodes of
+// the fluctuation (so that complex roots and non-finite states, which the FP64 path reports, do
+// not pass as FP32 rounding).
 template <int CL>
 __device__ __forceinline__ double speed_mixed(double h, double q, double g, const Closure &K,
                                               unsigned &bad)
 {
-    EigF E;
-    if (eigf<CL>((float)h, (float)q, (float)g, K, E))
-        return (double)(E.c * fmaxf(fmaxf(fabsf(E.mu1), fabsf(E.mu2)), fabsf(E.mu3)));
+    const float hf = (float)h, qf = (float)q, gf = (float)g;
+    const float gh = gf * hf;
+    const float t = __builtin_amdgcn_rsqf(gh * hf * hf);
+    const float Fr = qf * t;
+    const float inv_c = hf * t;
+    float k1, k2, b, kFr;
+    cubic_params<CL, float>(K, hf, qf, gf, Fr, inv_c, k1, k2, b, kFr);
+    const float r1 = __builtin_amdgcn_rsqf(k1);
+    const float x = (0.5f * k2) * (r1 * r1 * r1);
+    const float xa = Fr < 0.0f ? -x : x;
+    if (xa >= 0.0f && xa < 1.0f - kMixedFp64Band)
+        return (double)((gh * inv_c) * ((2.0f / 3.0f) * fmaf(k1 * r1, cos_third_acos(xa), fabsf(Fr))));
     return speed64<CL>(h, q, g, K, bad);
 }
 

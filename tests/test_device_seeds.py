@@ -181,3 +181,84 @@ def test_power_as_exp2_of_log2():
         got = np.exp2(y)
         bound = (2 * np.abs(y) * np.log(2) + 4) * 2.0 ** -53
         assert np.all(np.abs(got / a ** b - 1) <= bound), b
+
+
+def _poly_coeffs(sig):
+    """Horner coefficients (highest degree first) of a `p = ...; p = fma(p, t, c); ...` body."""
+    src = open(HDR).read()
+    body = src[src.index(sig):]
+    body = body[:body.index("\n}\n")]
+    lit = r"(-?\d+(?:\.\d+)?(?:e-?\d+)?)f?"
+    first = float(re.search(r"p = " + lit + ";", body).group(1))
+    # every Horner step, the returned last one included
+    rest = [float(v) for v in re.findall(r"fmaf?\(p, t, " + lit + r"\)", body)]
+    return [first] + rest
+
+
+def _fma(a, b, c):
+    from fractions import Fraction
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _cos_third_acos_f32(a32):
+    cs = _poly_coeffs("float cos_third_acos(float a)")
+    t = (np.float32(1) - a32).astype(np.float32)
+    p = np.full_like(a32, np.float32(cs[0]))
+    for c in cs[1:]:
+        p = (p.astype(np.float64) * t.astype(np.float64) + np.float64(np.float32(c))).astype(np.float32)
+    return p
+
+
+def test_cos_third_acos_fp64_newton():
+    # the CFL speed's cos(arccos(a)/3) on [0, 1] in FP64: the FP32 estimate, the FP32 reciprocal
+    # of the cubic's derivative, two Newton steps with correctly rounded FMAs as on the device;
+    # against 50-digit values: within 2 ulp
+    import mpmath as mp
+    mp.mp.dps = 40
+    src = open(HDR).read()
+    assert "for (int k = 0; k < 2; ++k) c = fma(-fma(c, fma(4.0 * c, c, -3.0), -a), r, c);" in src
+    pts = np.concatenate([np.linspace(0.0, 1.0, 2001), 1 - np.logspace(-16, -1, 200),
+                          np.logspace(-16, -1, 200)])
+    cf = _cos_third_acos_f32(pts.astype(np.float32))
+    d = (np.float32(12) * cf * cf - np.float32(3)).astype(np.float32)
+    r = (np.float32(1) / d).astype(np.float32)
+    worst = 0.0
+    for a, c0, rr in zip(pts, cf, r):
+        c, rr = float(c0), float(rr)
+        for _ in range(2):
+            f = _fma(c, _fma(4.0 * c, c, -3.0), -a)
+            c = _fma(-f, rr, c)
+        ref = mp.cos(mp.acos(mp.mpf(float(a))) / 3)
+        worst = max(worst, float(abs((mp.mpf(c) - ref) / ref)))
+    assert worst < 2 * 2.0 ** -52, worst
+
+
+def test_cos_third_acos_fp32_polynomial():
+    cs = _poly_coeffs("float cos_third_acos(float a)")
+    assert len(cs) == 8
+    a = np.concatenate([np.linspace(0.0, 1.0, 200001), 1 - np.logspace(-7, -1, 2000)]).astype(np.float32)
+    p = _cos_third_acos_f32(a)
+    ref = np.cos(np.arccos(a.astype(np.float64)) / 3)
+    assert np.max(np.abs(p - ref) / ref) < 4 * 2.0 ** -24
+
+
+def test_largest_speed_is_the_largest_root_at_abs_froude():
+    # the CFL speed takes max_m |mu_m| as mu_3 at |Fr| (k1 even, k2 odd in Fr); checked against
+    # all three roots over Froude numbers of both signs, transport from none to strong and both
+    # closure forms (kappa = 1 for velocity laws, 7/6 for stress laws), complex roots clamped
+    rng = np.random.default_rng(3)
+    n = 400_000
+    Fr = np.concatenate([rng.uniform(-10, 10, n), rng.uniform(-1.2, 1.2, n)])
+    b = np.concatenate([rng.exponential(1.0, n) * 10.0 ** rng.uniform(-8, 2, n), np.zeros(n)])
+    kap = np.where(rng.random(2 * n) < 0.5, 1.0, 7.0 / 6.0)
+
+    def roots(F):
+        k1 = 3 + F ** 2 + 3 * b
+        k2 = F * (18 - 2 * F ** 2 + (18 - 27 * kap) * b)
+        ph = np.arccos(np.clip(k2 / np.sqrt(4 * k1 ** 3), -1, 1))
+        m, f = 2 / 3 * np.sqrt(k1), 2 / 3 * F
+        return f - m * np.cos(ph / 3 - np.pi / 3), f - m * np.cos(ph / 3 + np.pi / 3), f + m * np.cos(ph / 3)
+
+    m1, m2, m3 = roots(Fr)
+    mx = np.maximum(np.maximum(np.abs(m1), np.abs(m2)), np.abs(m3))
+    assert np.max(np.abs(mx - roots(np.abs(Fr))[2]) / mx) < 1e-14

@@ -66,29 +66,32 @@ def test_pairwise_fluct_mixed(torch_dev, dsve, G):
         assert np.abs(got - ref).sum() / np.abs(ref).sum() <= TOL
 
 
-def _near_critical_edges(n, Ag, seed):
-    """Edges whose states sit at Froude numbers in [0.9, 1.1] (eigenvalues close to coalescing
-    when transport is weak)."""
-    rng = np.random.default_rng(seed)
-    h = rng.uniform(0.2, 2.0, n)
-    Fr = rng.uniform(0.9, 1.1, n)
-    u = Fr * np.sqrt(9.81 * h)
-    hR = h * (1 + 1e-3 * rng.uniform(-1, 1, n))
-    uR = u * (1 + 1e-3 * rng.uniform(-1, 1, n))
-    z = rng.uniform(-0.1, 0.1, n)
-    zR = z + 1e-3 * rng.uniform(-1, 1, n)
-    return (h, h * u, z), (hR, hR * uR, zR)
-
-
 @pytest.mark.parametrize("Ag", [1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
 def test_near_coalescence_stress(torch_dev, dsve, Ag):
-    # Fr in [0.9, 1.1] with weak transport: the two slow eigenvalues nearly coalesce and the
-    # arccos argument is close to 1.  The FP64 band keeps the mixed result at the FP32 level.
-    WL, WR = _near_critical_edges(100_000, Ag, seed=int(-np.log10(Ag)))
+    # Fr in [0.5, 1.5] with weak transport: near Fr = 1 the two slow eigenvalues nearly
+    # coalesce and the arccos argument is close to 1.  Nodes within the FP64 band go FP64; the
+    # rest, FP32, stay within the bar (the host study of test_mixed_band.py shows FP32 alone
+    # would not near coalescence).  Reported: the per-edge maximum, and the relative L1 over
+    # all edges, over the edges with every node outside the band (FP32 only) and over the rest.
+    from test_mixed_band import coalescence_distance, kernel_band, near_critical_edges
+    WL, WR = near_critical_edges(100_000, seed=int(-np.log10(Ag)))
     gm, gp = pairwise(dsve, torch_dev, WL, WR, Ag)
     rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, Ag)
-    for got, ref in ((gm, rm), (gp, rp)):
-        assert np.abs(got - ref).sum() / np.abs(ref).sum() <= TOL
+    d = coalescence_distance(WL, WR, Ag)
+    band = kernel_band()
+    fp32_only, fp64_node = d >= 1.05 * band, d < 0.95 * band
+    sc = np.abs(rm).max(axis=0) + np.abs(rp).max(axis=0)
+    per = np.maximum(np.abs(gm - rm).max(axis=0), np.abs(gp - rp).max(axis=0)) / sc
+
+    def l1(m):
+        return max(np.abs(g[:, m] - r[:, m]).sum() / np.abs(r[:, m]).sum()
+                   for g, r in ((gm, rm), (gp, rp))) if m.any() else 0.0
+
+    allm = np.ones_like(fp32_only)
+    print(f"A_g {Ag:.0e}: per-edge max {per.max():.2e}; L1 all {l1(allm):.2e}, FP32-only edges "
+          f"({fp32_only.mean():.3f}) {l1(fp32_only):.2e}, edges with FP64 nodes "
+          f"({fp64_node.mean():.3f}) {l1(fp64_node):.2e}")
+    assert l1(allm) <= TOL and l1(fp32_only) <= TOL and l1(fp64_node) <= TOL
 
 
 def test_c3_shape_reduced_full_length(torch_dev, dsve):
