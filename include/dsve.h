@@ -233,6 +233,19 @@ dsve_status adot_step(dsve_ctx *ctx, double *h, double *q, double *z, int n_step
 dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
                               double *t_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): adot_step / adot_step_batched for a context created
+ * beforehand, with the same results bit for bit, that allocates nothing -- no hipMalloc or
+ * hipFree, no graph instantiation (every step is a direct launch; the caller may capture them).
+ * The ping-pong copy of the state and clocks and the CFL slots live in a static device array
+ * of the library (about 24.4 MiB, held by each device the library runs on until the process
+ * ends) instead of the context's buffers, so the context may have at most 1048576 cells in at
+ * most 4096 channels; larger contexts get DSVE_E_ARG and keep using adot_step.  All calls on one
+ * device share that array: calls that overlap on one device (several streams or host threads)
+ * race and are not supported.  Errors are deferred to dsve_sync as for adot_step. */
+dsve_status adot_step_noalloc(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                              double *t_dev);
+
 /* Capture ahead the HIP graphs a run of n_steps on these arrays will replay (see adot_step),
  * so that the run itself only replays them: graph capture and instantiation then fall
  * outside a timed or latency-critical region.  Enqueues no work; the arrays are not read.

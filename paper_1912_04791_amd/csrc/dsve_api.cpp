@@ -76,6 +76,7 @@ struct dsve_ctx {
     // the last run: graph replays, the steps they ran, steps launched directly
     int last_graph_launches = 0, last_graph_steps = 0, last_direct = 0;
 
+    void *scratch = nullptr;   // device address of the static scratch (adot_step_noalloc)
     int last_amax_slot = -1;   // slot holding the CFL max of the latest state, or -1
     dsve_status sticky = DSVE_OK;
     std::string err;
@@ -241,6 +242,9 @@ static dsve_status setup(dsve_ctx *c, void *stream)
     HIP_TRY(c, hipMalloc(&c->d_flags, sizeof(unsigned int) * 4));
     HIP_TRY(c, launch_fill_u64(c->d_amax, 3 * c->amax_slot, 0ull, c->stream));
     HIP_TRY(c, launch_fill_u32(c->d_flags, 4, 0u, c->stream));
+    // the device address of the static scratch of adot_step_noalloc, looked up once per device
+    // (a failure leaves it null: that entry point then reports it, the others do not use it)
+    if (noalloc_scratch(c->device, &c->scratch) != hipSuccess) c->scratch = nullptr;
     dsve_status st = build_tile_table(c, c->tile);
     if (st != DSVE_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -530,28 +534,44 @@ static int split_of(const dsve_ctx *ctx, int grid)
     return (wg_per_channel >= 256.0 && tiles_per_wg <= 4.0) ? 4 : 1;
 }
 
+// The buffers a run rotates through besides the caller's: the ping-pong copy of the state and
+// clocks and the three CFL slots; the context's own, or the static scratch (adot_step_noalloc).
+struct RunBufs {
+    double *pp_h, *pp_q, *pp_z, *pp_t;
+    unsigned long long *amax;   // [3][kAmaxSplitMax][Cs]
+};
+static RunBufs ctx_bufs(const dsve_ctx *c) { return {c->pp_h, c->pp_q, c->pp_z, c->pp_t, c->d_amax}; }
+static RunBufs scratch_bufs(const dsve_ctx *c)
+{
+    char *base = static_cast<char *>(c->scratch);
+    double *st = reinterpret_cast<double *>(base + kNoAllocOffState);
+    return {st, st + c->n_cells, st + 2 * c->n_cells, reinterpret_cast<double *>(base + kNoAllocOffClock),
+            reinterpret_cast<unsigned long long *>(base + kNoAllocOffAmax)};
+}
+
 // Arguments of step j (phase j mod 6) of a run starting from the caller's buffers.
-static StepArgs step_args(dsve_ctx *ctx, int j, double *h, double *q, double *z, double *t)
+static StepArgs step_args(dsve_ctx *ctx, const RunBufs &b, int j, double *h, double *q, double *z,
+                          double *t)
 {
     StepArgs a{};
     const bool even = (j % 2) == 0;
-    a.h = even ? h : ctx->pp_h;
-    a.q = even ? q : ctx->pp_q;
-    a.z = even ? z : ctx->pp_z;
-    a.hn = even ? ctx->pp_h : h;
-    a.qn = even ? ctx->pp_q : q;
-    a.zn = even ? ctx->pp_z : z;
+    a.h = even ? h : b.pp_h;
+    a.q = even ? q : b.pp_q;
+    a.z = even ? z : b.pp_z;
+    a.hn = even ? b.pp_h : h;
+    a.qn = even ? b.pp_q : q;
+    a.zn = even ? b.pp_z : z;
     const int64_t C = ctx->n_channels;
     a.ch = ctx->d_ch;
     a.eoff = ctx->d_eoff;
     a.tile_chan = ctx->d_tile_chan;
-    a.amax_cur = ctx->d_amax + (j % 3) * ctx->amax_slot;
-    a.amax_next = ctx->d_amax + ((j + 1) % 3) * ctx->amax_slot;
-    a.amax_clear = ctx->d_amax + ((j + 2) % 3) * ctx->amax_slot;
+    a.amax_cur = b.amax + (j % 3) * ctx->amax_slot;
+    a.amax_next = b.amax + ((j + 1) % 3) * ctx->amax_slot;
+    a.amax_clear = b.amax + ((j + 2) % 3) * ctx->amax_slot;
     a.amax_stride = ctx->amax_cs;
     a.amax_split = split_of(ctx, grid_of(ctx));
-    a.t_cur = even ? t : ctx->pp_t;
-    a.t_next = even ? ctx->pp_t : t;
+    a.t_cur = even ? t : b.pp_t;
+    a.t_next = even ? b.pp_t : t;
     a.flags = ctx->d_flags;
     a.n_edges = ctx->n_edges;
     a.n_tiles = ctx->n_tiles;
@@ -567,8 +587,8 @@ static dsve_status capture_steps(dsve_ctx *ctx, int n, int grid, double *h, doub
     hipGraph_t graph = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < n; ++j) {
-        hipError_t e = launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
-                                   ctx->tile, grid, ctx->cap_stream);
+        hipError_t e = launch_step(step_args(ctx, ctx_bufs(ctx), j, h, q, z, t), ctx->precision, ctx->G,
+                                   ctx->cl, ctx->tile, grid, ctx->cap_stream);
         if (e != hipSuccess) {
             (void)hipStreamEndCapture(ctx->cap_stream, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -683,8 +703,8 @@ static dsve_status run_steps(dsve_ctx *ctx, double *h, double *q, double *z, int
     const int graph_done = done;
     const int grid = grid_of(ctx);
     for (int j = done; j < n_steps; ++j)
-        HIP_TRY(ctx, launch_step(step_args(ctx, j, h, q, z, t), ctx->precision, ctx->G, ctx->cl,
-                                 ctx->tile, grid, ctx->stream));
+        HIP_TRY(ctx, launch_step(step_args(ctx, ctx_bufs(ctx), j, h, q, z, t), ctx->precision, ctx->G,
+                                 ctx->cl, ctx->tile, grid, ctx->stream));
     ctx->last_graph_launches = launches;
     ctx->last_graph_steps = graph_done;
     ctx->last_direct = n_steps - graph_done;
@@ -735,6 +755,68 @@ dsve_status adot_step_batched(dsve_ctx *ctx, double *h, double *q, double *z, in
 {
     if (!ctx) return DSVE_E_ARG;
     return run_steps(ctx, h, q, z, n_steps, t_dev);
+}
+
+dsve_status adot_step_noalloc(dsve_ctx *ctx, double *h, double *q, double *z, int n_steps,
+                              double *t_dev)
+{
+    if (!ctx) return DSVE_E_ARG;
+    if (ctx->sticky != DSVE_OK) return ctx->sticky;
+    if (!h || !q || !z || !t_dev) return fail(ctx, DSVE_E_ARG, "null pointer");
+    if (n_steps < 0) return fail(ctx, DSVE_E_ARG, "n_steps must be >= 0");
+    if (ctx->n_cells > kNoAllocCells || ctx->n_channels > kNoAllocChannels)
+        return fail(ctx, DSVE_E_ARG,
+                    "adot_step_noalloc: the context exceeds its static scratch (at most " +
+                        std::to_string(kNoAllocCells) + " cells in " + std::to_string(kNoAllocChannels) +
+                        " channels); use adot_step or adot_step_batched");
+    if (!ctx->scratch) return fail(ctx, DSVE_E_HIP, "adot_step_noalloc: no static scratch on this device");
+    if (n_steps == 0) return DSVE_OK;
+    const RunBufs b = scratch_bufs(ctx);
+    if (ctx->resident_ok && ctx->resident_mode == 0) {
+        HIP_TRY(ctx, launch_fill_u64(b.amax, 3 * ctx->amax_slot, 0ull, ctx->stream));
+        ResidentArgs a{};
+        a.h = h; a.q = q; a.z = z; a.t = t_dev;
+        a.ch = ctx->d_ch; a.off = ctx->d_off; a.amax = b.amax; a.flags = ctx->d_flags;
+        a.n_channels = (int32_t)ctx->n_channels;
+        a.n_steps = n_steps;
+        a.g = ctx->g;
+        const int grid = (int)std::min<int64_t>(ctx->n_channels, (int64_t)(2048 / ctx->resident_threads) * ctx->cus);
+        HIP_TRY(ctx, launch_resident(a, ctx->precision, ctx->G, ctx->cl, ctx->resident_threads, grid,
+                                     ctx->stream));
+        // the final CFL maxima into the context's slot 0, where dsve_sync checks them
+        HIP_TRY(ctx, launch_copy_u64(ctx->d_amax, b.amax, ctx->amax_slot, ctx->stream));
+        ctx->last_amax_slot = 0;
+        ctx->last_graph_launches = 0;
+        ctx->last_graph_steps = 0;
+        ctx->last_direct = 1;
+        return DSVE_OK;
+    }
+    // the tile table of the current tile size exists from init or dsve_set_launch
+    if (!ctx->d_tile_chan || ctx->table_tile != ctx->tile)
+        return fail(ctx, DSVE_E_HIP, "adot_step_noalloc: no tile table for the current launch");
+    HIP_TRY(ctx, launch_fill_u64(b.amax, 3 * ctx->amax_slot, 0ull, ctx->stream));
+    dsve_status st = enqueue_cfl(ctx, h, q, z, b.amax);
+    if (st != DSVE_OK) return st;
+    const int grid = grid_of(ctx);
+    for (int j = 0; j < n_steps; ++j)
+        HIP_TRY(ctx, launch_step(step_args(ctx, b, j, h, q, z, t_dev), ctx->precision, ctx->G, ctx->cl,
+                                 ctx->tile, grid, ctx->stream));
+    if (n_steps % 2) {
+        const size_t bytes = sizeof(double) * ctx->n_cells;
+        HIP_TRY(ctx, hipMemcpyAsync(h, b.pp_h, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(q, b.pp_q, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(z, b.pp_z, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(t_dev, b.pp_t, sizeof(double) * ctx->n_channels,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    const int last = n_steps % 3;
+    HIP_TRY(ctx, launch_copy_u64(ctx->d_amax + last * ctx->amax_slot, b.amax + last * ctx->amax_slot,
+                                 ctx->amax_slot, ctx->stream));
+    ctx->last_amax_slot = last;
+    ctx->last_graph_launches = 0;
+    ctx->last_graph_steps = 0;
+    ctx->last_direct = n_steps;
+    return DSVE_OK;
 }
 
 dsve_status dsve_sync(dsve_ctx *ctx)

@@ -232,5 +232,21 @@ hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, 
                            hipStream_t stream);
 // kAmaxSplitMax as compiled into the kernels (the host code checks it against its own).
 int amax_split_of_kernels();
+hipError_t launch_copy_u64(unsigned long long *dst, const unsigned long long *src, int64_t n,
+                           hipStream_t stream);
+
+// Allocation-free runs (adot_step_noalloc): limits and layout of the static device scratch that
+// replaces the context's ping-pong state, clocks and CFL slots.
+constexpr int64_t kNoAllocCells = int64_t(1) << 20;
+constexpr int64_t kNoAllocChannels = 4096;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr int64_t kNoAllocSlotEntries = 3 * kAmaxSplitMax * ((kNoAllocChannels + 511) / 512 * 512);
+constexpr int64_t kNoAllocOffAmax = 0;                                              // uint64 [3][4][Cs]
+constexpr int64_t kNoAllocOffClock = kNoAllocOffAmax + 8 * kNoAllocSlotEntries;     // double [C]
+constexpr int64_t kNoAllocOffState = kNoAllocOffClock + 8 * kNoAllocChannels;       // double [3][N]
+constexpr int64_t kNoAllocScratchBytes = kNoAllocOffState + 3 * 8 * kNoAllocCells;
+static_assert(kNoAllocOffClock % 256 == 0 && kNoAllocOffState % 256 == 0, "scratch alignment");
+// Device address of the scratch on `device`, which must be the current device.
+hipError_t noalloc_scratch(int device, void **ptr);
 
 }  // namespace dsve

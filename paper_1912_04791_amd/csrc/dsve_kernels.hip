@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "dsve_dot.hpp"
 #include "dsve_internal.hpp"
 #include "dsve_math.hpp"
@@ -544,6 +546,20 @@ __global__ void k_fill_u32(unsigned int *p, int64_t n, unsigned int v)
     if (i < n) p[i] = v;
 }
 
+__global__ void k_copy_u64(unsigned long long *dst, const unsigned long long *src, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Static device scratch of the allocation-free run (adot_step_noalloc): the ping-pong copy of
+// the state and clocks and the rotating CFL slots of a run of at most kNoAllocCells cells in at
+// most kNoAllocChannels channels.  Each device the library runs on holds its own copy until the
+// process ends.  Host code never passes this name to a kernel: its device address comes from
+// hipGetSymbolAddress, once per device (noalloc_scratch below).
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 // ---------------------------------------------------------------------------
 static inline unsigned int blocks_for(int64_t n, int bs)
 {
@@ -760,5 +776,33 @@ hipError_t launch_resident(const ResidentArgs &a, int precision, int G, int cl, 
 }
 
 int amax_split_of_kernels() { return kAmaxSplitMax; }
+
+hipError_t launch_copy_u64(unsigned long long *dst, const unsigned long long *src, int64_t n,
+                           hipStream_t s)
+{
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_u64, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per device (the device
+// must be current; each device holds its own copy of the array at its own address).
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kNoAllocMaxDevices];
+
+hipError_t noalloc_scratch(int device, void **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace dsve

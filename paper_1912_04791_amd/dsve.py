@@ -123,6 +123,7 @@ lib.dsve_get_resident.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int)]
 lib.dsve_device_cus.argtypes = [_ctxp]
 lib.dsve_device_cus.restype = ctypes.c_int
 lib.dsve_prepare_run.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, _vp]
+lib.adot_step_noalloc.argtypes = [_ctxp, _vp, _vp, _vp, ctypes.c_int, _vp]
 lib.dsve_get_last_run.argtypes = [_ctxp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int)]
 assert lib.dsve_abi_version() == 5, "libdsve ABI version mismatch"
@@ -132,7 +133,7 @@ ENTRY_POINTS = ("dsve_abi_version", "dsve_init", "dsve_batch_init", "dsve_destro
                 "dsve_sync", "dsve_last_error", "dsve_clear_error", "dsve_set_launch",
                 "dsve_get_launch", "dsve_set_cfl_split", "dsve_get_cfl_split", "dsve_set_resident",
                 "dsve_get_resident", "dsve_autotune", "dsve_device_cus", "dsve_prepare_run",
-                "dsve_get_last_run")
+                "dsve_get_last_run", "adot_step_noalloc")
 
 
 class DsveError(RuntimeError):
@@ -326,6 +327,12 @@ class Context:
         fn = lib.adot_step_batched if self.batched else lib.adot_step
         self._check(fn(self._h, *self._state(h, q, z), int(n_steps),
                        _ptr(t, self.n_channels, device=self.device)), "adot_step")
+
+    def adot_step_noalloc(self, h, q, z, n_steps: int, t):
+        """adot_step without allocation (static device scratch; at most 2^20 cells, 4096 channels)."""
+        self._check(lib.adot_step_noalloc(self._h, *self._state(h, q, z), int(n_steps),
+                                          _ptr(t, self.n_channels, device=self.device)),
+                    "adot_step_noalloc")
 
     def prepare_run(self, h, q, z, n_steps: int, t):
         """Capture the graphs a run of n_steps on these tensors replays (no work enqueued)."""
