@@ -31,32 +31,35 @@
 
 namespace dsve {
 
-// Maximum over the 64 lanes of a wave of non-negative values (64-bit patterns), in lane 63,
-// read back to every lane.  DPP lane moves on the two 32-bit halves: swaps within quads,
-// half-row and row mirrors (each lane then holds its row of 16), then the broadcasts of lane
-// 15 of each row into the next row and of lane 31 into the upper half.  A lane whose DPP
-// source lies outside the wave reads 0, the identity of the maximum, so every lane is written
-// and no copy of the old value is needed.
+// Maximum over the 64 lanes of a wave of 32-bit values, read back to every lane.  DPP lane
+// moves (swaps within quads, half-row and row mirrors: each lane then holds its row of 16; then
+// the broadcasts of lane 15 of each row into the next row and of lane 31 into the upper half)
+// leave the maximum in lane 63.  A lane whose DPP source lies outside the wave reads 0, the
+// identity of the maximum, so every lane is written and no copy of the old value is needed.
 template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_umax(unsigned long long v)
+__device__ __forceinline__ unsigned dpp_umax32(unsigned v)
 {
-    const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
-    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
-    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
-    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
-    return (o > v) ? o : v;
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
+    return o > v ? o : v;
 }
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    v = dpp_umax32<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_umax32<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_umax32<0x141>(v);   // row_half_mirror
+    v = dpp_umax32<0x140>(v);   // row_mirror
+    v = dpp_umax32<0x142>(v);   // row_bcast:15
+    v = dpp_umax32<0x143>(v);   // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+// Maximum over the wave of 64-bit patterns: the largest high word, then the largest low word among
+// the lanes that hold it (one 32-bit maximum per step instead of a 64-bit compare and two selects).
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
-    v = dpp_umax<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v = dpp_umax<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-    v = dpp_umax<0x141>(v);   // row_half_mirror
-    v = dpp_umax<0x140>(v);   // row_mirror
-    v = dpp_umax<0x142>(v);   // row_bcast:15
-    v = dpp_umax<0x143>(v);   // row_bcast:31
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
+    const unsigned hi = (unsigned)(v >> 32), lo = (unsigned)v;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+    return ((unsigned long long)mh << 32) | ml;
 }
 
 // Per-channel maximum of `v` (bit patterns of non-negative doubles, so unsigned order is
@@ -205,12 +208,15 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const int h_bcl = nx_bcl, h_bcr = nx_bcr;
         const double am_home = nx_am;
         if (t == 0) s_acc = 0ull;
-        const Idx ge = (Idx)k * (Idx)(T - 1) + t;
-        const bool have_edge = ge < (Idx)A.n_edges;
+        // lanes past the last edge (in the last tile only) compute the last edge again: their
+        // results are never stored and no lane that updates a cell reads them
+        const Idx ge_raw = (Idx)k * (Idx)(T - 1) + t;
+        const bool have_edge = ge_raw < (Idx)A.n_edges;
+        const Idx ge = have_edge ? ge_raw : (Idx)A.n_edges - 1;
         int c = home;
         Idx eoc = eo0, cell0 = h_cell0, ncell = h_ncell;
         int bcl = h_bcl, bcr = h_bcr;
-        if (have_edge && ge >= eo1) {
+        if (ge >= eo1) {
             c = home + 1;
             while (ge >= (Idx)EO[c + 1]) ++c;
             eoc = (Idx)EO[c];
@@ -227,20 +233,16 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const Closure K = closure_of(ci);
         const Idx e = ge - eoc;
         unsigned bad = 0u;
-        double Dm[3] = {0.0, 0.0, 0.0}, Dp[3] = {0.0, 0.0, 0.0};
-        double hR = 0.0, qR = 0.0, zR = 0.0;
-        double hL = 0.0, qL = 0.0, zL = 0.0;
+        double Dm[3], Dp[3];
         const Idx N = ncell, base = cell0;
-        if (have_edge) {
-            const Idx il = (e == 0) ? (bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
-            const Idx ir = (e == N) ? (bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
-            hL = ldx<WIDE>(A.h, il);
-            qL = ldx<WIDE>(A.q, il);
-            zL = ldx<WIDE>(A.z, il);
-            hR = ldx<WIDE>(A.h, ir);
-            qR = ldx<WIDE>(A.q, ir);
-            zR = ldx<WIDE>(A.z, ir);
-        }
+        const Idx il = (e == 0) ? (bcl == BC_PERIODIC ? base + N - 1 : base) : base + e - 1;
+        const Idx ir = (e == N) ? (bcr == BC_PERIODIC ? base : base + N - 1) : base + e;
+        double hL = ldx<WIDE>(A.h, il);
+        double qL = ldx<WIDE>(A.q, il);
+        double zL = ldx<WIDE>(A.z, il);
+        const double hR = ldx<WIDE>(A.h, ir);
+        const double qR = ldx<WIDE>(A.q, ir);
+        const double zR = ldx<WIDE>(A.z, ir);
         // the next tile's lookups go out after this tile's state loads and before its
         // arithmetic, so waiting for the state does not wait for them
         __builtin_amdgcn_sched_barrier(0);
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             if (nx_home != home) nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
         }
         __builtin_amdgcn_sched_barrier(0);
-        if (have_edge) {
+        {
             double hRe = hR, qRe = qR, zRe = zR;
             if (e == 0) {
                 hL = ghost_h(ci.bcl, ci.bl, hL);

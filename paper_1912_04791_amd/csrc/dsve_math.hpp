@@ -283,29 +283,55 @@ struct Eig64 {
     double inv_gp;          // 1 / (g21 g31 g32)
 };
 
-// Error bits (kFlag*) go to `bad`: complex roots; a non-finite arccos argument; and an argument
-// of +-1 after the clamp, where two roots coalesce to working precision (sin(phi) = 0, so the
-// gap product and R^-1 do not exist).  Callers that need only the eigenvalues (the CFL speed)
-// drop the last bit.
+// Arccos argument x = k2 / sqrt(4 k1^3) of Eq. parameters at a state, with the quantities the
+// eigenstructure reuses: 1/sqrt(g h^3), Fr, 1/c, k1, b, kappa Fr and k1^(-1/2).
+template <int CL>
+struct ArgX {
+    double gh, Fr, inv_c, k1, b, kFr, r1, x;
+};
+template <int CL>
+__device__ __forceinline__ ArgX<CL> arg_x(double h, double q, double g, const Closure &K)
+{
+    ArgX<CL> a;
+    a.gh = g * h;
+    const double t = rsqrt_h(a.gh * h * h);   // 1 / sqrt(g h^3)
+    a.Fr = q * t;
+    a.inv_c = h * t;
+    double k2;
+    cubic_params<CL, double>(K, h, q, g, a.Fr, a.inv_c, a.k1, k2, a.b, a.kFr);
+    a.r1 = rsqrt_h(a.k1);
+    a.x = (0.5 * k2) * (a.r1 * a.r1 * a.r1);
+    return a;
+}
+
+// Error bits (kFlag*) from the largest |x| over a set of states, held as a bit pattern (a NaN
+// orders above every number): a NaN argument (an overflowed or NaN state, which the clamp would
+// turn into -1), complex roots (|x| beyond 1 + tol; k1 = 3 + Fr^2 + 3b > 0 for every closure, so
+// k1 <= 0 only comes with a NaN), and, with `coal`, an argument of +-1 after the clamp, where two
+// roots coalesce to working precision (sin(phi) = 0: the gap product and R^-1 do not exist).
+__device__ __forceinline__ unsigned arg_flags(unsigned long long xmax, bool coal)
+{
+    if (xmax > 0x7FF0000000000000ull) return kFlagNonfinite;
+    const double ax = __longlong_as_double((long long)xmax);
+    if (ax > 1.0 + kAcosTol) return kFlagComplex;
+    return (coal && ax >= 1.0) ? kFlagCoalesce : 0u;
+}
+__device__ __forceinline__ void track_arg(unsigned long long &xmax, double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(x));
+    xmax = b > xmax ? b : xmax;
+}
+
+// The largest |x| seen goes to `xmax` (classified by arg_flags).
 template <int CL>
 __device__ __forceinline__ void eig64(double h, double q, double g, const Closure &K, Eig64 &E,
-                                      unsigned &bad)
+                                      unsigned long long &xmax)
 {
-    const double gh = g * h;
-    const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
-    const double Fr = q * t;
-    const double inv_c = h * t;
-    double k1, k2, b, kFr;
-    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
-    const double r1 = rsqrt_h(k1);
-    const double r13 = r1 * r1 * r1;
-    double x = (0.5 * k2) * r13;   // k2 / sqrt(4 k1^3)
-    // complex roots: arccos argument beyond 1 + tol or k1 <= 0; a NaN argument (an overflowed
-    // or NaN state: fmax below would turn it into -1) is reported as non-finite
-    bad |= ((fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0)) ? kFlagComplex : 0u;
-    bad |= (x != x) ? kFlagNonfinite : 0u;
-    x = fmin(fmax(x, -1.0), 1.0);
-    bad |= (fabs(x) == 1.0) ? kFlagCoalesce : 0u;
+    const ArgX<CL> a = arg_x<CL>(h, q, g, K);
+    const double Fr = a.Fr, inv_c = a.inv_c, k1 = a.k1, b = a.b, kFr = a.kFr, r1 = a.r1;
+    const double gh = a.gh, r13 = r1 * r1 * r1;
+    track_arg(xmax, a.x);
+    const double x = fmin(fmax(a.x, -1.0), 1.0);
     double cs, sn, inv_y;
     trisect(x, cs, sn, inv_y);
     const double m = (2.0 / 3.0) * (k1 * r1);
@@ -364,16 +390,11 @@ __device__ __forceinline__ double cos_third_acos(double a)
 template <int CL>
 __device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, unsigned &bad)
 {
-    const double gh = g * h;
-    const double t = rsqrt_h(gh * h * h);   // 1 / sqrt(g h^3)
-    const double Fr = q * t;
-    const double inv_c = h * t;
-    double k1, k2, b, kFr;
-    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
-    const double r1 = rsqrt_h(k1);
-    const double x = (0.5 * k2) * (r1 * r1 * r1);
-    bad |= ((fabs(x) > 1.0 + kAcosTol) | (k1 <= 0.0)) ? kFlagComplex : 0u;
-    bad |= (x != x) ? kFlagNonfinite : 0u;
+    const ArgX<CL> a = arg_x<CL>(h, q, g, K);
+    const double Fr = a.Fr, k1 = a.k1, r1 = a.r1, x = a.x;
+    unsigned long long xmax = 0ull;
+    track_arg(xmax, x);
+    bad |= arg_flags(xmax, false);   // no R^-1 here: no coalescence bit
     const double xa = fmin(Fr < 0.0 ? -x : x, 1.0);
     double cth;
     if (xa >= 0.0) {
@@ -383,7 +404,7 @@ __device__ __forceinline__ double speed64(double h, double q, double g, const Cl
         trisect(fmax(xa, -1.0), cth, sn, inv_y);
     }
     // a NaN argument falls through both branches' arithmetic as NaN (the state is flagged)
-    return (gh * inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
+    return (a.gh * a.inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
 }
 
 // Accumulate one quadrature node: SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node,
@@ -427,13 +448,15 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
     double SA[3] = {dq, 0.0, 0.0}, SB[3] = {0.0, 0.0, 0.0};
+    unsigned long long xmax = 0ull;
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const double s = Gauss<G>::s[k];
         Eig64 E;
-        eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E, bad);
+        eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E, xmax);
         node_accumulate64(E, Gauss<G>::w[k], dh, dq, dz, SA, SB);
     }
+    bad |= arg_flags(xmax, true);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         Dm[r] = 0.5 * (SA[r] - SB[r]);
@@ -527,6 +550,7 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     const float gf = (float)g;
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
     double SA64[3] = {dq, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
+    unsigned long long xmax = 0ull;
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const float sf = (float)Gauss<G>::s[k];
@@ -536,10 +560,11 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
         } else {
             const double s = Gauss<G>::s[k];
             Eig64 E64;
-            eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, bad);
+            eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, xmax);
             node_accumulate64(E64, Gauss<G>::w[k], dh, dq, dz, SA64, SB64);
         }
     }
+    bad |= arg_flags(xmax, true);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const double A = (double)SA[r] + SA64[r], B = (double)SB[r] + SB64[r];
