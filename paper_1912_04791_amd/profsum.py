@@ -2,7 +2,7 @@
 
     python -m paper_1912_04791_amd.profsum --name k_step_c5_fp64 --kernel "k_step<3, 0, 0, false>" \
         --workload c5 --precision fp64 --trace DIR --bench-log FILE --bench-json FILE \
-        [--fetch DIR --write DIR --calib-mib 256] [--flops DIR] [--valu DIR] [--stall DIR] \
+        [--fetch DIR --write DIR --calib-mib 256] [--flops DIR] [--valu DIR] [--stall DIR ...] \
         --cmd "<the profiling commands>"
 
 Kernel trace (``--kernel-trace``): every GPU run bench.py makes is one ``k_cfl`` dispatch (the
@@ -155,7 +155,8 @@ def main():
     ap.add_argument("--write")
     ap.add_argument("--flops")
     ap.add_argument("--valu")
-    ap.add_argument("--stall")
+    ap.add_argument("--stall", nargs="*", default=[],
+                    help="counter runs (directories) whose counters are merged for the cycle shares")
     ap.add_argument("--calib-mib", type=int, default=256)
     ap.add_argument("--cmd", required=True, help="the profiling commands, verbatim")
     args = ap.parse_args()
@@ -257,8 +258,10 @@ def main():
             entry["valu_active_per_edge"] = act
             lines.append(f"- VALU-active 4-cycle units per edge update: {act:.0f}")
     if args.stall:
-        c, _ = counters(args.stall, args.kernel)
-        med = {k: statistics.median(v) for k, v in c.items()}
+        med = {}
+        for d in args.stall:
+            c, _ = counters(d, args.kernel)
+            med.update({k: statistics.median(v) for k, v in c.items()})
         lines += ["", "## Where the waves' cycles go (`--pmc`, quad-cycles summed over waves)", ""]
         for k in sorted(med):
             lines.append(f"- {k}: {med[k]:.6g}")
@@ -266,7 +269,9 @@ def main():
         if wc_:
             shares = {k: med[k] / wc_ for k in ("SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU",
                                                 "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY",
-                                                "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA")
+                                                "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS",
+                                                "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_VMEM",
+                                                "SQ_ACTIVE_INST_MISC")
                       if k in med}
             entry["wave_cycle_shares"] = shares
             lines.append("- shares of the wave-cycles: " +
