@@ -280,7 +280,7 @@ static ChanInfo make_chan(int64_t cell0, int64_t n, int law, const dsve_channel 
     const double xi = 1.0 / (1.0 - ch.porosity);
     ci.kqg = 3.0 * xi * ch.A_g * g;
     ci.K1 = 1.0 + 3.0 * ci.kqg;
-    ci.K2 = 2.0 + 9.0 * ci.kqg;
+    ci.K2h = 1.0 + 4.5 * ci.kqg;
     ci.cfl_dx = cfl * ch.dx;
     ci.inv_dx = 1.0 / ch.dx;
     // boundary data {h, q, z, dz/dt} of each end, as the ghost-state rules read them

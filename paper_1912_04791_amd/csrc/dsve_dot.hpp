@@ -247,8 +247,8 @@ __device__ __forceinline__ void flux_matrix(double h, double q, double g, const 
     const double t = rsqrt_h(gh * h * h);
     const double Fr = q * t;
     const double inv_c = h * t;
-    double k1, k2, b, kFr;
-    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
+    double k1, k2h, b, kFr;
+    cubic_params<CL, double>(K, h, q, g, Fr, inv_c, k1, k2h, b, kFr);
     const double c = gh * inv_c;
     const double u = Fr * c;
     A[0][0] = 0.0; A[0][1] = 1.0; A[0][2] = 0.0;

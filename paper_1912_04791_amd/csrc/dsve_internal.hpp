@@ -94,7 +94,7 @@ struct alignas(16) ChanInfo {
     int64_t cell0;   // first cell of the channel in the concatenated state
     int64_t ncell;   // N_c
     double kqg;      // 3 xi A_g g: xi dq_s/dq = kqg Fr^2 for the Grass law
-    double K1, K2;   // 1 + 3 kqg, 2 + 9 kqg (k1 = 3 + K1 Fr^2, k2 = Fr (18 - K2 Fr^2))
+    double K1, K2h;   // 1 + 3 kqg, 1 + 4.5 kqg (k1 = 3 + K1 Fr^2, k2 / 2 = Fr (9 - K2h Fr^2))
     double cfl_dx;   // cfl * dx  (dt = cfl_dx / amax)
     double inv_dx;   // 1 / dx
     double fric;     // 1 / K_s^2 of the friction slope (0: no friction source)

@@ -458,13 +458,23 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(CflArgs A)
     int cur = home;                // the wave's current channel
     unsigned long long acc = 0ull; // this lane's maximum over its cells in `cur`
     unsigned bad = 0u;
+    // the lane's channel end and closure stay in registers until the lane leaves the channel,
+    // so the common iteration waits only for its own cell's state
+    int64_t c_end = A.off[c + 1];
+    Closure K = closure_of(A.ch[c]);
     for (int64_t i0 = start; i0 < end; i0 += kCflThreads) {
         const int64_t i = i0 + threadIdx.x;
         const bool active = i < end;
         unsigned long long bits = 0ull;
         if (active) {
-            while (i >= A.off[c + 1]) ++c;
-            const double sp = fabs(cell_speed<PREC, CL>(A.h[i], A.q[i], A.g, closure_of(A.ch[c]), bad));
+            if (i >= c_end) {
+                do {
+                    ++c;
+                    c_end = A.off[c + 1];
+                } while (i >= c_end);
+                K = closure_of(A.ch[c]);
+            }
+            const double sp = fabs(cell_speed<PREC, CL>(A.h[i], A.q[i], A.g, K, bad));
             bits = (unsigned long long)__double_as_longlong(sp);
         }
         const unsigned long long moved = __ballot(active && c != cur);

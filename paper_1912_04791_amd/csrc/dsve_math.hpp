@@ -40,20 +40,16 @@
 // Arithmetic kernels (own implementations of published methods):
 //   rcp_h / rsqrt_h: hardware reciprocal / reciprocal-square-root estimate (about 2^-24
 //     relative) refined by one Halley step (cubic convergence, about 2^-72).
-//   trisect: cos(theta), sin(theta), theta = arccos(x)/3.  An FP32 estimate of theta gives a
-//     point on the unit circle, renormalised in FP64; the residual angle follows from the
-//     complex identity Im(w conj(z)^3) = sin(phi - 3 theta0), w = x + i sqrt(1 - x^2),
-//     z = cos(theta0) + i sin(theta0), and a rotation by residual/3 (second-order sine and
-//     cosine of a small angle) removes it, leaving an error of order (residual)^3.  The
-//     estimate is arccos(a) = sqrt(1 - a) P(a), a = |x|, with 1 - a formed in FP64 (so the
-//     square-root behaviour at |x| -> 1 keeps its relative accuracy) and P of degree 5
-//     fitted by least squares on Chebyshev nodes of [0, 1]; its error stays below 1.4e-6
-//     in FP32 arithmetic, which one correction takes below FP64 rounding.
+//   third_angle: cos(theta), sin(theta), theta = arccos(a)/3 for a = |x| in [0, 1], where the
+//     function is analytic (its branch point is at a = -1): the cosine C from a degree-7
+//     polynomial in 1 - a (FP32) and two Newton steps on the trisection cubic 4C^3 - 3C = a
+//     (FP64), the sine from sin(3 theta) = S (4C^2 - 1), i.e. S = sqrt(1 - a^2) / (4C^2 - 1),
+//     with 4C^2 - 1 in [2, 3].  The roots at -x are those at x negated, so the eigenvalues are
+//     sign(x) {C, -P, -Q} about f, P, Q = C/2 +- (sqrt3/2) S, labelled in that order, not sorted:
+//     every sum over the three eigenpairs is symmetric in the labels.
 //   Gap product: (mu_2 - mu_1)(mu_3 - mu_1)(mu_3 - mu_2) = (3 sqrt3 / 4) m^3 sin(3 theta)
 //     = (2 sqrt3 / 9) k1^(3/2) sin(phi), so its reciprocal is (3 sqrt3 / 2) k1^(-3/2) / sin(phi),
 //     from the k1^(-1/2) and 1/sin(phi) the roots already need.
-//   In the mixed form the FP32 arccos is the degree-7 approximation of Abramowitz & Stegun
-//     (Handbook, 4.4.46; error below 2e-8).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,77 +90,17 @@ __device__ __forceinline__ double rsqrt_h(double x)
     return fma(r * e, fma(e, 0.375, 0.5), r);
 }
 
-// One correction of (c, s) ~ (cos theta, sin theta) towards 3 theta = phi, cos(phi) = x,
-// sin(phi) = y >= 0; (c, s) unit length to rounding.
-__device__ __forceinline__ void trisect_correct(double x, double y, double &c, double &s)
-{
-    const double C3 = c * fma(4.0 * c, c, -3.0);   // cos(3 theta0)
-    const double S3 = s * fma(-4.0 * s, s, 3.0);   // sin(3 theta0)
-    const double d = fma(y, C3, -x * S3) * (1.0 / 3.0);   // sin(phi - 3 theta0) / 3
-    const double cd = fma(-0.5 * d, d, 1.0);
-    const double cn = fma(c, cd, -s * d);
-    const double sn = fma(s, cd, c * d);
-    c = cn;
-    s = sn;
-}
-
-// FP32 estimate of arccos(x), x in [-1, 1], for the trisection (see the header).
-__device__ __forceinline__ float acos_seed(double x)
-{
-    const double ax = fabs(x);
-    const float a = (float)ax;
-    float p = fmaf(a, -0.004258281551301479f, 0.01915096305310726f);
-    p = fmaf(a, p, -0.044784508645534515f);
-    p = fmaf(a, p, 0.08781391382217407f);
-    p = fmaf(a, p, -0.21450453996658325f);
-    p = fmaf(a, p, 1.5707950592041016f);
-    const float r = p * __builtin_amdgcn_sqrtf((float)(1.0 - ax));
-    return x < 0.0 ? 3.14159265358979f - r : r;
-}
-
-// FP32 arccos for the mixed form (Abramowitz & Stegun 4.4.46, degree 7).
-__device__ __forceinline__ float acos_f32(float x)
-{
-    const float a = fabsf(x);
-    float p = fmaf(a, -0.0012624911f, 0.0066700901f);
-    p = fmaf(a, p, -0.0170881256f);
-    p = fmaf(a, p, 0.0308918810f);
-    p = fmaf(a, p, -0.0501743046f);
-    p = fmaf(a, p, 0.0889789874f);
-    p = fmaf(a, p, -0.2145988016f);
-    p = fmaf(a, p, 1.5707963050f);
-    const float r = p * __builtin_amdgcn_sqrtf(1.0f - a);
-    return x < 0.0f ? 3.14159265358979f - r : r;
-}
-
-// (cos theta, sin theta), theta = arccos(x) / 3, and 1 / sin(3 theta), x in [-1, 1] (NaN
-// propagates; at x = +-1 the reciprocal is huge but finite).
-__device__ __forceinline__ void trisect(double x, double &c, double &s, double &inv_y)
-{
-    const double v = fma(-x, x, 1.0);
-    inv_y = rsqrt_h(fmax(v, 1e-300));
-    const double y = v * inv_y;   // sin(phi); 0 at x = +-1, NaN stays NaN
-    const float th0 = acos_seed(x) * (1.0f / 3.0f);
-    const double c0 = (double)__cosf(th0), s0 = (double)__sinf(th0);
-    // renormalise: 1/sqrt(c0^2 + s0^2) to second order in e = c0^2 + s0^2 - 1 (|e| ~ 1e-7)
-    const double e = fma(c0, c0, fma(s0, s0, -1.0));
-    const double nr = fma(e, fma(e, 0.375, -0.5), 1.0);
-    c = c0 * nr;
-    s = s0 * nr;
-    trisect_correct(x, y, c, s);
-}
-
 // ---------------------------------------------------------------------------
-// Per-channel constants of the closure: kqg = 3 xi A_g g, K1 = 1 + 3 kqg, K2 = 2 + 9 kqg for
+// Per-channel constants of the closure: kqg = 3 xi A_g g, K1 = 1 + 3 kqg, K2h = 1 + 4.5 kqg for
 // the Grass law in closed form; the law and its constants lp0, lp1 for the general form.
 struct Closure {
-    double kqg, K1, K2;
+    double kqg, K1, K2h;
     double lp0, lp1;
     int law, ipow;
 };
 __device__ __forceinline__ Closure closure_of(const ChanInfo &ci)
 {
-    return Closure{ci.kqg, ci.K1, ci.K2, ci.lp0, ci.lp1, ci.law, ci.ipow};
+    return Closure{ci.kqg, ci.K1, ci.K2h, ci.lp0, ci.lp1, ci.law, ci.ipow};
 }
 
 // FP64 power a^b, a > 0, as 2^(b log2 a): a relative error of about 2 |b log2 a| ulp, a few ulp
@@ -253,27 +189,87 @@ __device__ __forceinline__ T law_b(const Closure &K, T h, T q, T invh)
     }
 }
 
-// Cubic parameters k1, k2 (Eqs. parameters, parameters_bis), b and kappa Fr at a state.
+// Cubic parameters k1, k2 / 2 (Eqs. parameters, parameters_bis), b and kappa Fr at a state (the
+// halved k2 is exact: every term is halved).
 template <int CL, typename T>
 __device__ __forceinline__ void cubic_params(const Closure &K, T h, T q, T g, T Fr, T inv_c,
-                                             T &k1, T &k2, T &b, T &kFr)
+                                             T &k1, T &k2h, T &b, T &kFr)
 {
     const T Fr2 = Fr * Fr;
     if constexpr (CL == CL_GRASS) {
         b = T(K.kqg) * Fr2;
         k1 = fma(Fr2, T(K.K1), T(3));
-        k2 = Fr * fma(-Fr2, T(K.K2), T(18));
+        k2h = Fr * fma(-Fr2, T(K.K2h), T(9));
         kFr = Fr;
     } else {
         const T invh = g * (inv_c * inv_c);   // c^2 = g h
         b = law_b<CL, T>(K, h, q, invh);
         constexpr bool stress = CL == CL_MPM || CL == CL_VANRIJN;
-        const T kk = stress ? T(-13.5) : T(-9);   // 18 - 27 kappa
+        const T kk = stress ? T(-6.75) : T(-4.5);   // (18 - 27 kappa) / 2
         k1 = fma(T(3), b, fma(Fr, Fr, T(3)));
-        k2 = Fr * fma(kk, b, fma(T(-2) * Fr, Fr, T(18)));
+        k2h = Fr * fma(kk, b, fma(-Fr, Fr, T(9)));
         kFr = stress ? T(7.0 / 6.0) * Fr : Fr;
     }
 }
+
+// cos(arccos(a) / 3) for a in [0, 1] in FP32: the function is analytic there (its branch point is
+// at a = -1); a polynomial of degree 7 in t = 1 - a, interpolated at the Chebyshev nodes of
+// [0, 1] in 50-digit arithmetic, meets it to about 1 ulp in FP32.
+__device__ __forceinline__ float cos_third_acos(float a)
+{
+    const float t = 1.0f - a;
+    float p = -0.0005426077404990792f;
+    p = fmaf(p, t, 0.0008754234877415001f);
+    p = fmaf(p, t, -0.0015220807399600744f);
+    p = fmaf(p, t, -0.0008192436653189361f);
+    p = fmaf(p, t, -0.004411802161484957f);
+    p = fmaf(p, t, -0.01644226536154747f);
+    p = fmaf(p, t, -0.11111201345920563f);
+    return fmaf(p, t, 1.0f);
+}
+// The same in FP64: C = cos(arccos(a) / 3) is the root in [cos(pi/6), 1] of the trisection cubic
+// f(C) = 4C^3 - 3C - a, whose derivative 12C^2 - 3 is at least 6 there.  From the FP32 estimate,
+// two Newton steps in FP64 dividing by the derivative taken once in FP32: each takes an error e to
+// about e * 1e-7 + e^2 (1e-7 -> 4e-14 -> FP64 rounding).  Its FP32 constants are instruction
+// literals, so nothing stays in registers between calls.  r receives the FP32 reciprocal of the
+// derivative.
+__device__ __forceinline__ double cos_third_acos(double a, double &r)
+{
+    const float cf = cos_third_acos((float)a);
+    r = (double)__builtin_amdgcn_rcpf(fmaf(12.0f * cf, cf, -3.0f));
+    double c = (double)cf;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) c = fma(-fma(c, fma(4.0 * c, c, -3.0), -a), r, c);
+    return c;
+}
+__device__ __forceinline__ double cos_third_acos(double a)
+{
+    double r;
+    return cos_third_acos(a, r);
+}
+
+// cos(theta) and sin(theta) for theta = arccos(a) / 3, a in [0, 1] (theta in [0, pi/6]), given
+// y = sin(3 theta) = sqrt(1 - a^2).  Since sin(3 theta) = S (3 - 4 S^2) = S (4 C^2 - 1) and
+// 4 C^2 - 1 lies in [2, 3], S = y / (4 C^2 - 1) keeps the relative accuracy of y as a -> 1,
+// where S -> 0 (no cancellation, unlike sqrt(1 - C^2)).  The reciprocal 1 / (4 C^2 - 1) is three
+// times the FP32 reciprocal of the derivative above, refined by one Halley step (e ~ 1e-7 ->
+// e^3).
+__device__ __forceinline__ void third_angle(double a, double y, double &C, double &S)
+{
+    double r;
+    C = cos_third_acos(a, r);
+    const double u = fma(4.0 * C, C, -1.0);
+    const double R0 = 3.0 * r;
+    const double e = fma(-u, R0, 1.0);
+    S = y * fma(R0, fma(e, e, e), R0);
+}
+// The same in FP32 (the polynomial alone; one rounded reciprocal).
+__device__ __forceinline__ void third_angle(float a, float y, float &C, float &S)
+{
+    C = cos_third_acos(a);
+    S = y * __builtin_amdgcn_rcpf(fmaf(4.0f * C, C, -1.0f));
+}
+
 
 // FP64 non-dimensional eigenstructure at one state.
 struct Eig64 {
@@ -297,10 +293,10 @@ __device__ __forceinline__ ArgX<CL> arg_x(double h, double q, double g, const Cl
     const double t = rsqrt_h(a.gh * h * h);   // 1 / sqrt(g h^3)
     a.Fr = q * t;
     a.inv_c = h * t;
-    double k2;
-    cubic_params<CL, double>(K, h, q, g, a.Fr, a.inv_c, a.k1, k2, a.b, a.kFr);
+    double k2h;
+    cubic_params<CL, double>(K, h, q, g, a.Fr, a.inv_c, a.k1, k2h, a.b, a.kFr);
     a.r1 = rsqrt_h(a.k1);
-    a.x = (0.5 * k2) * (a.r1 * a.r1 * a.r1);
+    a.x = k2h * (a.r1 * a.r1 * a.r1);
     return a;
 }
 
@@ -332,61 +328,36 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     const double gh = a.gh, r13 = r1 * r1 * r1;
     track_arg(xmax, a.x);
     const double x = fmin(fmax(a.x, -1.0), 1.0);
-    double cs, sn, inv_y;
-    trisect(x, cs, sn, inv_y);
+    const double v = fma(-x, x, 1.0);
+    const double inv_y = rsqrt_h(fmax(v, 1e-300));   // 1 / sin(phi), huge but finite at x = +-1
+    double C, S;
+    third_angle(fabs(x), v * inv_y, C, S);
+    // roots about f: sign(x) m {C, -P, -Q}, P, Q = C/2 +- r, labelled 1, 2, 3 in that order
     const double m = (2.0 / 3.0) * (k1 * r1);
+    const double ms = copysign(m, x);
     const double f = (2.0 / 3.0) * Fr;
-    const double p = 0.5 * cs, r = kSqrt3Half * sn;
+    const double r = kSqrt3Half * S;
     E.Fr = Fr;
     E.c = gh * inv_c;
     E.inv_c = inv_c;
     E.b = b;
     E.kFr = kFr;
-    E.mu1 = f - m * (p + r);
-    E.mu2 = f - m * (p - r);
-    E.mu3 = fma(m, cs, f);
-    E.g21 = (2.0 * m) * r;
-    E.g31 = m * fma(3.0, p, r);
-    E.g32 = m * fma(3.0, p, -r);
-    E.inv_gp = (kInvGapScale * r13) * inv_y;
-}
-
-// cos(arccos(a) / 3) for a in [0, 1] in FP32: the function is analytic there (its branch point is
-// at a = -1); a polynomial of degree 7 in t = 1 - a, interpolated at the Chebyshev nodes of
-// [0, 1] in 50-digit arithmetic, meets it to about 1 ulp in FP32.
-__device__ __forceinline__ float cos_third_acos(float a)
-{
-    const float t = 1.0f - a;
-    float p = -0.0005426077404990792f;
-    p = fmaf(p, t, 0.0008754234877415001f);
-    p = fmaf(p, t, -0.0015220807399600744f);
-    p = fmaf(p, t, -0.0008192436653189361f);
-    p = fmaf(p, t, -0.004411802161484957f);
-    p = fmaf(p, t, -0.01644226536154747f);
-    p = fmaf(p, t, -0.11111201345920563f);
-    return fmaf(p, t, 1.0f);
-}
-// The same in FP64: C = cos(arccos(a) / 3) is the root in [cos(pi/6), 1] of the trisection cubic
-// f(C) = 4C^3 - 3C - a, whose derivative 12C^2 - 3 is at least 6 there.  From the FP32 estimate,
-// two Newton steps in FP64 dividing by the derivative taken once in FP32: each takes an error e to
-// about e * 1e-7 + e^2 (1e-7 -> 4e-14 -> FP64 rounding).  Its FP32 constants are instruction
-// literals, so nothing stays in registers between calls.
-__device__ __forceinline__ double cos_third_acos(double a)
-{
-    const float cf = cos_third_acos((float)a);
-    const double r = (double)__builtin_amdgcn_rcpf(fmaf(12.0f * cf, cf, -3.0f));
-    double c = (double)cf;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) c = fma(-fma(c, fma(4.0 * c, c, -3.0), -a), r, c);
-    return c;
+    E.mu1 = fma(ms, C, f);
+    E.mu2 = fma(-ms, fma(0.5, C, r), f);
+    E.mu3 = fma(-ms, fma(0.5, C, -r), f);
+    E.g21 = -ms * fma(1.5, C, r);    // mu2 - mu1 = -ms (P + C)
+    E.g31 = -ms * fma(1.5, C, -r);   // mu3 - mu1 = -ms (Q + C)
+    E.g32 = (2.0 * ms) * r;          // mu3 - mu2 = ms (P - Q)
+    // 1 / (g21 g31 g32): the gap product is sign(x) (3 sqrt3 / 4) m^3 sin(phi)
+    E.inv_gp = (copysign(kInvGapScale, x) * r13) * inv_y;
 }
 
 // Largest characteristic speed max_m |lambda_m| of a cell state (the CFL quantity).  k1 is even
 // and k2 odd in Fr, so the spectrum at -Fr is the negation of the spectrum at Fr, and the largest
 // |mu| is the largest root at |Fr|: mu_3 = (2/3)(|Fr| + sqrt(k1) cos(theta')), theta' =
 // arccos(x')/3 with x' = x sign(Fr) the arccos argument at |Fr|.  For x' >= 0 (|Fr| below about 3
-// under weak transport) the cosine comes from the polynomial above; for x' < 0 from the
-// trisection of the fluctuation nodes.
+// under weak transport) the cosine is cos_third_acos(x'); for x' < 0 it follows from the angle
+// at -x' (third_angle).
 template <int CL>
 __device__ __forceinline__ double speed64(double h, double q, double g, const Closure &K, unsigned &bad)
 {
@@ -400,8 +371,12 @@ __device__ __forceinline__ double speed64(double h, double q, double g, const Cl
     if (xa >= 0.0) {
         cth = cos_third_acos(xa);
     } else {
-        double sn, inv_y;
-        trisect(fmax(xa, -1.0), cth, sn, inv_y);
+        // theta' = pi/3 - theta for a = -x': cos(theta') = C/2 + (sqrt3/2) S
+        const double na = fmin(-xa, 1.0);
+        const double v = fma(-na, na, 1.0);
+        double C, S;
+        third_angle(na, v * rsqrt_h(fmax(v, 1e-300)), C, S);
+        cth = fma(0.5, C, kSqrt3Half * S);
     }
     // a NaN argument falls through both branches' arithmetic as NaN (the state is flagged)
     return (a.gh * a.inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
@@ -423,21 +398,22 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
     const double n1 = fma(fma(mu2, mu3, base), dh, fma(mu1, dqn, dz));
     const double n2 = fma(fma(mu3, mu1, base), dh, fma(mu2, dqn, dz));
     const double n3 = fma(fma(mu1, mu2, base), dh, fma(mu3, dqn, dz));
-    // w |mu_i| (l_i . dW), denominators 1/d_1 = g32/P, 1/d_2 = -g31/P, 1/d_3 = g21/P
-    const double wP = w * E.inv_gp;
-    const double b1 = n1 * (fabs(mu1) * E.g32) * wP;
-    const double b2 = -n2 * (fabs(mu2) * E.g31) * wP;
-    const double b3 = n3 * (fabs(mu3) * E.g21) * wP;
+    // |mu_i| (l_i . dW) up to the common factor 1/P of the denominators 1/d_1 = g32/P,
+    // 1/d_2 = -g31/P, 1/d_3 = g21/P, which enters once per row with w and c or c^2
+    const double b1 = n1 * (fabs(mu1) * E.g32);
+    const double b2 = -n2 * (fabs(mu2) * E.g31);
+    const double b3 = n3 * (fabs(mu3) * E.g21);
     const double e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
     const double B0 = b1 + b2 + b3;
     const double B1 = fma(b1, mu1, fma(b2, mu2, b3 * mu3));
     const double B2 = fma(b1, fma(e1, e1, -1.0), fma(b2, fma(e2, e2, -1.0), b3 * fma(e3, e3, -1.0)));
-    const double wc = w * c;
-    SA[1] = fma(wc * c, A1n, SA[1]);
+    const double wc = w * c, wcc = wc * c;
+    const double wcP = wc * E.inv_gp, wccP = wcc * E.inv_gp;
+    SA[1] = fma(wcc, A1n, SA[1]);
     SA[2] = fma(wc, A2n, SA[2]);
-    SB[0] = fma(c, B0, SB[0]);
-    SB[1] = fma(c * c, B1, SB[1]);
-    SB[2] = fma(c, B2, SB[2]);
+    SB[0] = fma(wcP, B0, SB[0]);
+    SB[1] = fma(wccP, B1, SB[1]);
+    SB[2] = fma(wcP, B2, SB[2]);
 }
 
 // DOT fluctuations of one edge, FP64 throughout.
@@ -474,6 +450,7 @@ struct EigF {
     float Fr, c, inv_c, b, kFr;
     float mu1, mu2, mu3;
     float g21, g31, g32;
+    float inv_gp;
 };
 
 // Returns false when the node must be evaluated in FP64 (the FP32 argument only selects
@@ -485,27 +462,38 @@ __device__ __forceinline__ bool eigf(float h, float q, float g, const Closure &K
     const float t = __builtin_amdgcn_rsqf(gh * h * h);
     const float Fr = q * t;
     const float inv_c = h * t;
-    float k1, k2, b, kFr;
-    cubic_params<CL, float>(K, h, q, g, Fr, inv_c, k1, k2, b, kFr);
+    float k1, k2h, b, kFr;
+    cubic_params<CL, float>(K, h, q, g, Fr, inv_c, k1, k2h, b, kFr);
     const float r1 = __builtin_amdgcn_rsqf(k1);
-    float x = (0.5f * k2) * (r1 * r1 * r1);
+    const float r13 = r1 * r1 * r1;
+    const float x = k2h * r13;
     if (!(fabsf(x) < 1.0f - kMixedFp64Band)) return false;
-    const float th = acos_f32(x) * (1.0f / 3.0f);
-    const float cs = __cosf(th), sn = __sinf(th);
+    const float v = fmaf(-x, x, 1.0f);
+    const float inv_y = __builtin_amdgcn_rsqf(v);
+    const float a = fabsf(x);
+    float C, S;
+    third_angle(a, v * inv_y, C, S);
+    // the roots and gaps as in eig64
     const float m = (2.0f / 3.0f) * (k1 * r1);
+    const float ms = copysignf(m, x);
     const float f = (2.0f / 3.0f) * Fr;
-    const float p = 0.5f * cs, r = (float)kSqrt3Half * sn;
+    const float r = (float)kSqrt3Half * S;
     E.Fr = Fr;
     E.c = gh * inv_c;
     E.inv_c = inv_c;
     E.b = b;
     E.kFr = kFr;
-    E.mu1 = f - m * (p + r);
-    E.mu2 = f - m * (p - r);
-    E.mu3 = fmaf(m, cs, f);
-    E.g21 = (2.0f * m) * r;
-    E.g31 = m * fmaf(3.0f, p, r);
-    E.g32 = m * fmaf(3.0f, p, -r);
+    // Q = C/2 - r = sin(arcsin(a)/3) cancels as a -> 0, where Q ~ a/3: there it comes from its
+    // series a/3 + 4a^3/81 + O(a^5) (relative error below 1e-8 for a < 1/64), so that near still
+    // water (Fr -> 0) the bed speed keeps its relative accuracy and is exactly 0 at Fr = 0
+    const float Q = a < 0.015625f ? a * fmaf(a * a, 4.0f / 81.0f, 1.0f / 3.0f) : fmaf(0.5f, C, -r);
+    E.mu1 = fmaf(ms, C, f);
+    E.mu2 = fmaf(-ms, fmaf(0.5f, C, r), f);
+    E.mu3 = fmaf(-ms, Q, f);
+    E.g21 = -ms * fmaf(1.5f, C, r);
+    E.g31 = -ms * (C + Q);
+    E.g32 = (2.0f * ms) * r;
+    E.inv_gp = (copysignf((float)kInvGapScale, x) * r13) * inv_y;
     return true;
 }
 
@@ -523,20 +511,20 @@ __device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float d
     const float n1 = fmaf(fmaf(mu2, mu3, nF2), dh, fmaf(mu1, dqn, eta));
     const float n2 = fmaf(fmaf(mu3, mu1, nF2), dh, fmaf(mu2, dqn, eta));
     const float n3 = fmaf(fmaf(mu1, mu2, nF2), dh, fmaf(mu3, dqn, eta));
-    const float wP = w * __builtin_amdgcn_rcpf(E.g21 * E.g31 * E.g32);
-    const float b1 = n1 * (fabsf(mu1) * E.g32) * wP;
-    const float b2 = -n2 * (fabsf(mu2) * E.g31) * wP;
-    const float b3 = n3 * (fabsf(mu3) * E.g21) * wP;
+    const float b1 = n1 * (fabsf(mu1) * E.g32);
+    const float b2 = -n2 * (fabsf(mu2) * E.g31);
+    const float b3 = n3 * (fabsf(mu3) * E.g21);
     const float e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
     const float B0 = b1 + b2 + b3;
     const float B1 = fmaf(b1, mu1, fmaf(b2, mu2, b3 * mu3));
     const float B2 = fmaf(b1, fmaf(e1, e1, -1.0f), fmaf(b2, fmaf(e2, e2, -1.0f), b3 * fmaf(e3, e3, -1.0f)));
-    const float wc = w * c;
-    SA[1] = fmaf(wc * c, A1n, SA[1]);
+    const float wc = w * c, wcc = wc * c;
+    const float wcP = wc * E.inv_gp, wccP = wcc * E.inv_gp;
+    SA[1] = fmaf(wcc, A1n, SA[1]);
     SA[2] = fmaf(wc, A2n, SA[2]);
-    SB[0] = fmaf(c, B0, SB[0]);
-    SB[1] = fmaf(c * c, B1, SB[1]);
-    SB[2] = fmaf(c, B2, SB[2]);
+    SB[0] = fmaf(wcP, B0, SB[0]);
+    SB[1] = fmaf(wccP, B1, SB[1]);
+    SB[2] = fmaf(wcP, B2, SB[2]);
 }
 
 template <int G, int CL>
@@ -548,8 +536,9 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     const float dhf = (float)dh, dqf = (float)dq, etaf = (float)(dh + dz);
     const float hLf = (float)hL, qLf = (float)qL;
     const float gf = (float)g;
+    // the node sums in FP32 (row 0 of S_A is dq, in FP64); a node in the band is evaluated in FP64
+    // and its terms, which no longer carry the FP32 error near coalescence, are added rounded
     float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
-    double SA64[3] = {dq, 0.0, 0.0}, SB64[3] = {0.0, 0.0, 0.0};
     unsigned long long xmax = 0ull;
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
@@ -561,15 +550,21 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
             const double s = Gauss<G>::s[k];
             Eig64 E64;
             eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, xmax);
-            node_accumulate64(E64, Gauss<G>::w[k], dh, dq, dz, SA64, SB64);
+            double NA[3] = {0.0, 0.0, 0.0}, NB[3] = {0.0, 0.0, 0.0};
+            node_accumulate64(E64, Gauss<G>::w[k], dh, dq, dz, NA, NB);
+            SA[1] += (float)NA[1];
+            SA[2] += (float)NA[2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) SB[r] += (float)NB[r];
         }
     }
     bad |= arg_flags(xmax, true);
+    const double A[3] = {dq, (double)SA[1], (double)SA[2]};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const double A = (double)SA[r] + SA64[r], B = (double)SB[r] + SB64[r];
-        Dm[r] = 0.5 * (A - B);
-        Dp[r] = 0.5 * (A + B);
+        const double B = (double)SB[r];
+        Dm[r] = 0.5 * (A[r] - B);
+        Dp[r] = 0.5 * (A[r] + B);
     }
 }
 
@@ -586,10 +581,10 @@ __device__ __forceinline__ double speed_mixed(double h, double q, double g, cons
     const float t = __builtin_amdgcn_rsqf(gh * hf * hf);
     const float Fr = qf * t;
     const float inv_c = hf * t;
-    float k1, k2, b, kFr;
-    cubic_params<CL, float>(K, hf, qf, gf, Fr, inv_c, k1, k2, b, kFr);
+    float k1, k2h, b, kFr;
+    cubic_params<CL, float>(K, hf, qf, gf, Fr, inv_c, k1, k2h, b, kFr);
     const float r1 = __builtin_amdgcn_rsqf(k1);
-    const float x = (0.5f * k2) * (r1 * r1 * r1);
+    const float x = k2h * (r1 * r1 * r1);
     const float xa = Fr < 0.0f ? -x : x;
     if (xa >= 0.0f && xa < 1.0f - kMixedFp64Band)
         return (double)((gh * inv_c) * ((2.0f / 3.0f) * fmaf(k1 * r1, cos_third_acos(xa), fabsf(Fr))));

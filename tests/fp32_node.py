@@ -9,12 +9,14 @@ oracle instead.
 
 Rounding model: every FP32 operation rounds once, an FMA is the exact product (a float64
 product of two floats is exact) plus the addend rounded to FP32 (two roundings where the device
-rounds once, a difference of at most one ulp in rare cases); the reciprocal square root,
-reciprocal, cosine and sine are rounded correctly, where the device approximates them to one or
-two ulp.  The model's FP32 error therefore slightly understates the device's; the band-on
+rounds once, a difference of at most one ulp in rare cases); the reciprocal square root and
+reciprocal are rounded correctly, where the device approximates them to about one ulp.  The model's FP32 error therefore slightly understates the device's; the band-on
 figures of the tests come from the device itself.
 """
 from __future__ import annotations
+
+import os
+import re
 
 import numpy as np
 
@@ -37,16 +39,35 @@ def add(a, b):
     return _r(np.asarray(a, dtype=np.float64) + np.asarray(b, dtype=np.float64))
 
 
-def acos_f32(x):
-    """Abramowitz & Stegun 4.4.46 (degree 7), as the mixed form evaluates it."""
-    a = np.abs(x)
-    cs = [-0.0012624911, 0.0066700901, -0.0170881256, 0.0308918810, -0.0501743046, 0.0889789874,
-          -0.2145988016, 1.5707963050]
-    p = fmaf(a, np.full_like(a, f32(cs[0])), f32(cs[1]))
-    for c in cs[2:]:
-        p = fmaf(a, p, f32(c))
-    r = mul(p, _r(np.sqrt((f32(1) - a).astype(np.float64))))
-    return np.where(x < 0, add(f32(3.14159265358979), -r), r).astype(np.float32)
+def rsq(x):
+    return _r(1.0 / np.sqrt(np.asarray(x, dtype=np.float64)))
+
+
+def rcp(x):
+    return _r(1.0 / np.asarray(x, dtype=np.float64))
+
+
+def _cos_third_acos_coeffs():
+    """Horner coefficients (highest degree first) of the kernels' FP32 cos(arccos(a)/3)."""
+    src = open(os.path.join(os.path.dirname(__file__), "..", "paper_1912_04791_amd", "csrc",
+                            "dsve_math.hpp")).read()
+    body = src[src.index("float cos_third_acos(float a)"):]
+    body = body[:body.index("\n}\n")]
+    lit = r"(-?\d+(?:\.\d+)?(?:e-?\d+)?)f?"
+    first = float(re.search(r"p = " + lit + ";", body).group(1))
+    return [first] + [float(v) for v in re.findall(r"fmaf?\(p, t, " + lit + r"\)", body)]
+
+
+_CT = _cos_third_acos_coeffs()
+
+
+def cos_third_acos_f32(a):
+    """cos(arccos(a)/3), a in [0, 1]: the degree-7 polynomial in 1 - a, in FP32."""
+    t = add(f32(1), -a)
+    p = np.full_like(t, f32(_CT[0]))
+    for c in _CT[1:]:
+        p = fmaf(p, t, f32(c))
+    return p
 
 
 def node_terms(h, q, dh, dq, eta, w, g, kqg, band):
@@ -64,22 +85,31 @@ def node_terms(h, q, dh, dq, eta, w, g, kqg, band):
     b = mul(f32(kqg), Fr2)
     k1 = fmaf(Fr2, np.full_like(Fr2, K1), f32(3))
     k2 = mul(Fr, fmaf(-Fr2, np.full_like(Fr2, K2), f32(18)))
-    r1 = _r(1.0 / np.sqrt(k1.astype(np.float64)))
-    x = mul(mul(f32(0.5), k2), mul(mul(r1, r1), r1))
+    r1 = rsq(k1)
+    r13 = mul(mul(r1, r1), r1)
+    x = mul(mul(f32(0.5), k2), r13)
     inband = ~(np.abs(x) < f32(1) - f32(band)) if band > 0 else np.zeros(x.shape, dtype=bool)
     xc = np.clip(x, f32(-1), f32(1))
-    th = mul(acos_f32(xc), f32(1.0 / 3.0))
-    cs, sn = _r(np.cos(th.astype(np.float64))), _r(np.sin(th.astype(np.float64)))
+    v = np.maximum(fmaf(-xc, xc, f32(1)), f32(1e-30))
+    inv_y = rsq(v)
+    C = cos_third_acos_f32(np.abs(xc))
+    S = mul(mul(v, inv_y), rcp(fmaf(mul(f32(4), C), C, f32(-1))))
     m = mul(f32(2.0 / 3.0), mul(k1, r1))
+    ms = np.copysign(m, xc).astype(np.float32)
     f = mul(f32(2.0 / 3.0), Fr)
-    p, rr = mul(f32(0.5), cs), mul(f32(0.86602540378443864676), sn)
+    rr = mul(f32(0.86602540378443864676), S)
     c = mul(gh, inv_c)
-    mu1 = fmaf(-m, add(p, rr), f)
-    mu2 = fmaf(-m, add(p, -rr), f)
-    mu3 = fmaf(m, cs, f)
-    g21 = mul(mul(f32(2), m), rr)
-    g31 = mul(m, fmaf(np.full_like(p, f32(3)), p, rr))
-    g32 = mul(m, fmaf(np.full_like(p, f32(3)), p, -rr))
+    # the roots sign(x) m {C, -P, -Q} about f, unsorted (the sums are symmetric in the labels)
+    mu1 = fmaf(ms, C, f)
+    mu2 = fmaf(-ms, fmaf(np.full_like(C, f32(0.5)), C, rr), f)
+    aa = np.abs(xc)
+    ser = mul(aa, fmaf(mul(aa, aa), np.full_like(aa, f32(4 / 81)), f32(1 / 3)))
+    Q = np.where(aa < f32(1 / 64), ser, fmaf(np.full_like(C, f32(0.5)), C, -rr)).astype(np.float32)
+    mu3 = fmaf(-ms, Q, f)
+    g21 = mul(-ms, fmaf(np.full_like(C, f32(1.5)), C, rr))
+    g31 = mul(-ms, add(C, Q))
+    g32 = mul(mul(f32(2), ms), rr)
+    inv_gp = mul(mul(np.copysign(f32(2.59807621135331594029), xc).astype(np.float32), r13), inv_y)
     dqn = mul(dq, inv_c)
     nF2 = -Fr2
     A1n = fmaf(nF2, dh, fmaf(mul(f32(2), Fr), dqn, eta))
@@ -87,17 +117,18 @@ def node_terms(h, q, dh, dq, eta, w, g, kqg, band):
     n1 = fmaf(fmaf(mu2, mu3, nF2), dh, fmaf(mu1, dqn, eta))
     n2 = fmaf(fmaf(mu3, mu1, nF2), dh, fmaf(mu2, dqn, eta))
     n3 = fmaf(fmaf(mu1, mu2, nF2), dh, fmaf(mu3, dqn, eta))
-    wP = mul(w, _r(1.0 / mul(mul(g21, g31), g32).astype(np.float64)))
-    b1 = mul(mul(n1, mul(np.abs(mu1), g32)), wP)
-    b2 = mul(mul(-n2, mul(np.abs(mu2), g31)), wP)
-    b3 = mul(mul(n3, mul(np.abs(mu3), g21)), wP)
+    b1 = mul(n1, mul(np.abs(mu1), g32))
+    b2 = mul(-n2, mul(np.abs(mu2), g31))
+    b3 = mul(n3, mul(np.abs(mu3), g21))
     e1, e2, e3 = add(Fr, -mu1), add(Fr, -mu2), add(Fr, -mu3)
     B0 = add(add(b1, b2), b3)
     B1 = fmaf(b1, mu1, fmaf(b2, mu2, mul(b3, mu3)))
     B2 = fmaf(b1, fmaf(e1, e1, f32(-1)), fmaf(b2, fmaf(e2, e2, f32(-1)), mul(b3, fmaf(e3, e3, f32(-1)))))
     wc = mul(w, c)
-    SA = (mul(mul(wc, c), A1n), mul(wc, A2n))
-    SB = (mul(c, B0), mul(mul(c, c), B1), mul(c, B2))
+    wcc = mul(wc, c)
+    wcP, wccP = mul(wc, inv_gp), mul(wcc, inv_gp)
+    SA = (mul(wcc, A1n), mul(wc, A2n))
+    SB = (mul(wcP, B0), mul(wccP, B1), mul(wcP, B2))
     return SA, SB, inband
 
 

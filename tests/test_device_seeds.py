@@ -1,9 +1,10 @@
-"""Accuracy of the FP32 arccos approximations the device code uses (host-side checks of the
-coefficients in dsve_math.hpp, evaluated in FP32 as the kernels evaluate them).
+"""Host-side checks of the arithmetic kernels in dsve_math.hpp (coefficients read from the
+header, evaluated in FP32 or with correctly rounded FMAs as the kernels evaluate them).
 
-The FP64 trisection takes an FP32 estimate of arccos(x) and corrects it once; the correction
-leaves an error of order (estimate error / 3)^3, so an estimate good to a few 1e-6 is enough.
-The mixed form uses its FP32 arccos directly, so it must be as good as a library FP32 arccos.
+The eigenvalues come from cos and sin of theta = arccos(|x|)/3: the cosine from an FP32
+polynomial refined by Newton steps in FP64, the sine from sin(3 theta) = S (4 C^2 - 1).  The
+roots at -x are those at x negated, so the kernels label the roots sign(x) {C, -P, -Q} without
+sorting them.
 """
 import os
 import re
@@ -13,71 +14,100 @@ import numpy as np
 HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1912_04791_amd", "csrc", "dsve_math.hpp")
 
 
-def _coeffs(fn):
-    """Horner coefficients (highest degree first) and the reflection constant pi of `fn`."""
+def test_roots_labelled_by_the_sign_of_x_are_the_trisection_roots():
+    # sign(x) {C, -P, -Q}, P, Q = C/2 +- (sqrt3/2) S, with (C, S) at arccos(|x|)/3, is the set
+    # {cos(phi/3), cos(phi/3 +- 2 pi/3)}, phi = arccos(x); the gaps of the labels and their
+    # product sign(x) (3 sqrt3 / 4) sin(phi), whose reciprocal the kernels take
+    x = np.concatenate([np.linspace(-1.0, 1.0, 20001), -1 + np.logspace(-12, -1, 200),
+                        1 - np.logspace(-12, -1, 200)])
+    th = np.arccos(np.abs(x)) / 3
+    C, S = np.cos(th), np.sin(th)
+    sg = np.copysign(1.0, x)
+    r = np.sqrt(3) / 2 * S
+    lab = np.stack([sg * C, -sg * (0.5 * C + r), -sg * (0.5 * C - r)])
+    ph = np.arccos(x) / 3
+    ref = np.stack([np.cos(ph), np.cos(ph + 2 * np.pi / 3), np.cos(ph - 2 * np.pi / 3)])
+    np.testing.assert_allclose(np.sort(lab, axis=0), np.sort(ref, axis=0), rtol=0, atol=2e-15)
+    g21 = -sg * (1.5 * C + r)
+    g31 = -sg * (1.5 * C - r)
+    g32 = 2 * sg * r
+    np.testing.assert_allclose(g21, lab[1] - lab[0], rtol=0, atol=4e-15)
+    np.testing.assert_allclose(g31, lab[2] - lab[0], rtol=0, atol=4e-15)
+    np.testing.assert_allclose(g32, lab[2] - lab[1], rtol=0, atol=4e-15)
+    np.testing.assert_allclose(g21 * g31 * g32, sg * 3 * np.sqrt(3) / 4 * np.sin(np.arccos(x)),
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_third_angle_fp64():
+    # (C, S) in FP64 as the kernels compute them: the FP32 polynomial, the FP32 reciprocal of the
+    # cubic's derivative, two Newton steps, then S = y / (4C^2 - 1) with 1 / (4C^2 - 1) = 3r
+    # refined by one Halley step, every FMA correctly rounded; y = sqrt(1 - a^2) correctly
+    # rounded.  Against 40-digit values: C within 2 ulp, S within 4 ulp relative (also as
+    # a -> 1, where S -> 0)
+    import mpmath as mp
+    mp.mp.dps = 40
     src = open(HDR).read()
-    body = src[src.index(f"float {fn}("):]
+    body = src[src.index("void third_angle(double a, double y, double &C, double &S)"):]
     body = body[:body.index("\n}\n")]
-    lit = r"(-?\d+\.\d+(?:e-?\d+)?)f"
-    first = re.search(r"fmaf\(a, " + lit + ", " + lit + r"\)", body)
-    rest = re.findall(r"fmaf\(a, p, " + lit + r"\)", body)
-    pi_f = float(re.search(r"\? " + lit + " - r", body).group(1))
-    return [float(first.group(1)), float(first.group(2))] + [float(v) for v in rest], pi_f
+    for line in ("const double u = fma(4.0 * C, C, -1.0);", "const double R0 = 3.0 * r;",
+                 "const double e = fma(-u, R0, 1.0);", "S = y * fma(R0, fma(e, e, e), R0);"):
+        assert line in body, line
+    pts = np.concatenate([np.linspace(0.0, 1.0, 601), 1 - np.logspace(-16, -1, 120),
+                          np.logspace(-16, -1, 60)])
+    cf = _cos_third_acos_f32(pts.astype(np.float32))
+    d = (np.float32(12) * cf * cf - np.float32(3)).astype(np.float32)
+    rr = (np.float32(1) / d).astype(np.float32)
+    worst_c = worst_s = 0.0
+    for a, c0, r in zip(pts, cf, rr):
+        c, r = float(c0), float(r)
+        for _ in range(2):
+            c = _fma(-_fma(c, _fma(4.0 * c, c, -3.0), -a), r, c)
+        u = _fma(4.0 * c, c, -1.0)
+        R0 = 3.0 * r
+        e = _fma(-u, R0, 1.0)
+        y = float(mp.sqrt(1 - mp.mpf(float(a)) ** 2))
+        S = y * _fma(R0, _fma(e, e, e), R0)
+        th = mp.acos(mp.mpf(float(a))) / 3
+        worst_c = max(worst_c, float(abs((mp.mpf(c) - mp.cos(th)) / mp.cos(th))))
+        if a < 1.0:
+            worst_s = max(worst_s, float(abs((mp.mpf(S) - mp.sin(th)) / mp.sin(th))))
+    assert worst_c < 2 * 2.0 ** -52, worst_c
+    assert worst_s < 4 * 2.0 ** -52, worst_s
 
 
-def _horner_f32(cs, a):
-    p = np.float32(cs[0])
-    for c in cs[1:]:
-        p = (a * p + np.float32(c)).astype(np.float32)
-    return p
+def test_third_angle_fp32():
+    # the mixed form's (C, S): the polynomial and S = y * rcp(4C^2 - 1) in FP32, y correctly
+    # rounded to FP32; against FP64 values: C within 4 ulp, S within 6 ulp relative
+    a = np.concatenate([np.linspace(0.0, 1.0, 200001), 1 - np.logspace(-7, -1, 2000)]).astype(np.float32)
+    C = _cos_third_acos_f32(a)
+    y = np.sqrt(1 - a.astype(np.float64) ** 2).astype(np.float32)
+    u = (np.float32(4) * C * C - np.float32(1)).astype(np.float32)
+    S = (y * (np.float32(1) / u).astype(np.float32)).astype(np.float32)
+    th = np.arccos(a.astype(np.float64)) / 3
+    assert np.max(np.abs(C - np.cos(th)) / np.cos(th)) < 4 * 2.0 ** -24
+    m = a < 1
+    assert np.max(np.abs(S[m] - np.sin(th[m])) / np.sin(th[m])) < 6 * 2.0 ** -24
 
 
-def _estimate(fn, x64, one_minus_in_fp64):
-    cs, pi_f = _coeffs(fn)
-    ax = np.abs(x64)
-    a = ax.astype(np.float32)
-    p = _horner_f32(cs, a)
-    om = (1.0 - ax).astype(np.float32) if one_minus_in_fp64 else (np.float32(1) - a)
-    r = (p * np.sqrt(om)).astype(np.float32)
-    return np.where(x64 < 0, np.float32(pi_f) - r, r).astype(np.float64)
-
-
-def _grid():
-    near = np.logspace(-16, -1, 4000)
-    return np.concatenate([np.linspace(-1.0, 1.0, 400001), 1 - near, -1 + near])
-
-
-def test_trisection_seed_error_bound():
-    x = _grid()
-    err = np.abs(_estimate("acos_seed", x, True) - np.arccos(x))
-    assert err.max() < 1.5e-6, err.max()
-
-
-def test_trisection_seed_then_one_correction_reaches_fp64():
-    # one correction of the trisection from the estimate (FP32 cosine and sine of theta0/3),
-    # as in the kernels: the result agrees with cos/sin(arccos(x)/3) to a few ulp
-    x = _grid()
-    th0 = (_estimate("acos_seed", x, True).astype(np.float32) * np.float32(1 / 3)).astype(np.float32)
-    c = np.cos(th0).astype(np.float32).astype(np.float64)
-    s = np.sin(th0).astype(np.float32).astype(np.float64)
-    e = c * c + s * s - 1
-    nr = 1 + e * (-0.5 + 0.375 * e)
-    c, s = c * nr, s * nr
-    y = np.sqrt(np.maximum((1 - x) * (1 + x), 0))
-    C3, S3 = c * (4 * c * c - 3), s * (3 - 4 * s * s)
-    d = (y * C3 - x * S3) / 3
-    cd = 1 - 0.5 * d * d
-    c, s = c * cd - s * d, s * cd + c * d
-    th = np.arccos(x) / 3
-    assert np.abs(c - np.cos(th)).max() < 2e-15
-    assert np.abs(s - np.sin(th)).max() < 2e-15
-
-
-def test_mixed_form_arccos_matches_an_fp32_library_arccos():
-    x = np.linspace(-1.0, 1.0, 400001).astype(np.float32).astype(np.float64)
-    ours = np.abs(_estimate("acos_f32", x, False) - np.arccos(x)).max()
-    lib = np.abs(np.arccos(x.astype(np.float32)).astype(np.float64) - np.arccos(x)).max()
-    assert ours < 5e-7 and ours < 1.5 * lib, (ours, lib)
+def test_small_root_series_in_fp32():
+    # the mixed form's Q = C/2 - r = sin(arcsin(a)/3), which cancels as a -> 0, comes from its
+    # series a/3 + 4a^3/81 below a = 1/64: within 1e-8 relative of the function there (FP64
+    # evaluation), and within 3 ulp when evaluated in FP32 as the kernel does
+    src = open(HDR).read()
+    assert "a < 0.015625f ? a * fmaf(a * a, 4.0f / 81.0f, 1.0f / 3.0f) : fmaf(0.5f, C, -r)" in src
+    a = np.concatenate([np.linspace(0.0, 1 / 64, 20001), np.logspace(-30, np.log10(1 / 64), 400)])
+    ref = np.sin(np.arcsin(a) / 3)
+    ser = a * (a * a * 4 / 81 + 1 / 3)
+    m = a > 0
+    assert np.max(np.abs(ser[m] - ref[m]) / ref[m]) < 1e-8
+    a32 = a.astype(np.float32)
+    aa = (a32 * a32).astype(np.float32)
+    inner = (aa.astype(np.float64) * np.float64(np.float32(4 / 81)) + np.float64(np.float32(1 / 3))).astype(np.float32)
+    s32 = (a32 * inner).astype(np.float32)
+    ref32 = np.sin(np.arcsin(a32.astype(np.float64)) / 3)
+    m = a32 > 0
+    assert np.max(np.abs(s32[m] - ref32[m]) / ref32[m]) < 3 * 2.0 ** -24
+    assert s32[0] == 0.0
 
 
 def test_gap_product_identity():

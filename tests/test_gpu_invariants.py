@@ -45,10 +45,11 @@ def run(dsve, wl, precision, steps=None):
 def test_lake_at_rest_is_preserved(torch_dev, dsve, precision, bar, n_cells):
     wl = inputs.make_lake_at_rest(n_cells=n_cells, steps=300)
     h, q, z, t = run(dsve, wl, precision)
+    dev = (np.max(np.abs(q)), np.max(np.abs(h + z - 1.0)), np.max(np.abs(z - wl.z)))
+    print(f"lake at rest, {precision}, {n_cells} cells, 300 steps: max |q| {dev[0]:.2e}, "
+          f"max |h + z - 1| {dev[1]:.2e}, max |z - z0| {dev[2]:.2e}")
     assert t[0] > 0
-    assert np.max(np.abs(q)) < bar
-    assert np.max(np.abs(h + z - 1.0)) < bar
-    assert np.max(np.abs(z - wl.z)) < bar
+    assert max(dev) < bar
 
 
 # The c1 dam break with A_g = 0: shallow water over a 0.2 m bed step, the bed fixed.  The middle
