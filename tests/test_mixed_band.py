@@ -62,12 +62,20 @@ def rel_l1(got, ref, m):
 BINS = [0.0, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2, 3e-2, 1e-1, 1.0]
 
 
-@pytest.mark.parametrize("Ag", [1e-5, 1e-6, 1e-7, 1e-8])
+@pytest.mark.parametrize("Ag", [1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8])
 def test_fp32_error_grows_toward_coalescence_and_the_band_covers_it(Ag):
     WL, WR = near_critical_edges(100_000, seed=int(-np.log10(Ag)))
     ref = oracle.fluct(WL, WR, 9.81, XI, Ag)
     got = fp32_node.fluct_fp32(WL, WR, 9.81, XI, Ag)[:2]
     d = coalescence_distance(WL, WR, Ag)
+    # the same edges and edge classes as the GPU sweep of test_gpu_mixed.py (band on), here
+    # with every node in FP32 (band off)
+    b = kernel_band()
+    fp32_only, fp64_node = d >= 1.05 * b, d < 0.95 * b
+    print(f"A_g {Ag:.0e}, band off: L1 all {rel_l1(got, ref, np.ones_like(d, bool)):.2e}, FP32-only "
+          f"edges ({fp32_only.mean():.3f}) {rel_l1(got, ref, fp32_only):.2e}, edges with a node in the "
+          f"band ({fp64_node.mean():.3f}) "
+          f"{rel_l1(got, ref, fp64_node) if fp64_node.any() else 0.0:.2e}")
     rows = []
     for lo, hi in zip(BINS[:-1], BINS[1:]):
         m = (d >= lo) & (d < hi)
