@@ -63,11 +63,11 @@ constexpr int kCflThreads = 1024;  // threads per workgroup of the CFL-maximum k
 #ifndef DSVE_MINW_LAW_MIXED
 #define DSVE_MINW_LAW_MIXED 2
 #endif
-// The FP64 integer-exponent power law fits 4 waves with a 20-byte spill, which pays (its ensemble
-// steps 4% faster); MPM and Van Rijn spill 56 bytes there and run 12% slower, so they keep the
-// floor of 2 and run the 3 waves their 143-145 registers allow.
+// The FP64 integer-exponent power law runs the 3 waves its 146 registers allow: capped for 4
+// waves it spills 140 bytes and its ensemble steps 26% slower.  MPM and Van Rijn keep the floor
+// of 2 and run 3 waves as well (157 registers).
 #ifndef DSVE_MINW_POWINT_FP64
-#define DSVE_MINW_POWINT_FP64 4
+#define DSVE_MINW_POWINT_FP64 3
 #endif
 #ifndef DSVE_MINW_DOT
 #define DSVE_MINW_DOT 2
