@@ -3,6 +3,7 @@
     python -m paper_1912_04791_amd.profsum --name k_step_c5_fp64 --kernel "k_step<3, 0, 0, false>" \
         --workload c5 --precision fp64 --trace DIR --bench-log FILE --bench-json FILE \
         [--fetch DIR --write DIR --calib-mib 256] [--flops DIR] [--valu DIR] [--stall DIR ...] \
+        [--clock DIR] \
         --cmd "<the profiling commands>"
 
 Kernel trace (``--kernel-trace``): every GPU run bench.py makes is one ``k_cfl`` dispatch (the
@@ -116,6 +117,25 @@ def counters(pmc_dir: str, kernel: str):
     return out, first
 
 
+def clock_per_dispatch(run_dir: str, kernel: str, n_xcd: int = 8):
+    """Effective shader clock of each dispatch of the kernel from a run that took the kernel trace
+    and GRBM_GUI_ACTIVE (GPU-busy cycles, summed over the XCDs) together: cycles / XCDs /
+    duration.  Returns a list of (duration in s, clock in Hz, counters of the dispatch)."""
+    tr = list(csv.DictReader(open(_one(os.path.join(run_dir, "**", "*kernel_trace.csv")))))
+    cc = list(csv.DictReader(open(_one(os.path.join(run_dir, "**", "*counter_collection.csv")))))
+    dur = {int(r["Dispatch_Id"]): (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+           for r in tr if kernel in r["Kernel_Name"]}
+    per = {}
+    for r in cc:
+        if kernel in r["Kernel_Name"]:
+            per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = []
+    for d, c in sorted(per.items()):
+        if d in dur and "GRBM_GUI_ACTIVE" in c and dur[d] > 0:
+            out.append((dur[d], c["GRBM_GUI_ACTIVE"] / n_xcd / dur[d], c))
+    return out
+
+
 def valu_flops(c):
     """FP64 and FP32 VALU FLOPs per dispatch from the instruction counters: 64 lanes per wave
     instruction, an FMA counted twice (medians over the dispatches)."""
@@ -157,6 +177,7 @@ def main():
     ap.add_argument("--valu")
     ap.add_argument("--stall", nargs="*", default=[],
                     help="counter runs (directories) whose counters are merged for the cycle shares")
+    ap.add_argument("--clock", help="a run with --kernel-trace and --pmc GRBM_GUI_ACTIVE together")
     ap.add_argument("--calib-mib", type=int, default=256)
     ap.add_argument("--cmd", required=True, help="the profiling commands, verbatim")
     args = ap.parse_args()
@@ -281,6 +302,23 @@ def main():
                 entry["valu_busy"] = busy
                 lines.append(f"- VALU busy: {busy:.3f} of the 1024 SIMDs' 4-cycle issue slots at "
                              "the events step time")
+    if args.clock:
+        rows = clock_per_dispatch(args.clock, args.kernel)
+        if rows:
+            clk = statistics.median(r[1] for r in rows)
+            dur_ = statistics.median(r[0] for r in rows)
+            entry["clock_ghz"] = clk / 1e9
+            lines += ["", "## Effective clock (`--kernel-trace` with `--pmc GRBM_GUI_ACTIVE` in one run)", "",
+                      f"- {len(rows)} dispatches, median duration {dur_ * 1e6:.1f} us under the counters; "
+                      f"GRBM_GUI_ACTIVE / 8 XCDs / duration: median {clk / 1e9:.3f} GHz (min "
+                      f"{min(r[1] for r in rows) / 1e9:.3f}, max {max(r[1] for r in rows) / 1e9:.3f}), "
+                      "against the 2.4 GHz of the published peaks"]
+            act = [r[2].get("SQ_ACTIVE_INST_VALU") for r in rows]
+            if all(a is not None for a in act):
+                busy = statistics.median(a * 4.0 / (1024 * d * f) for a, (d, f, _) in zip(act, rows))
+                entry["valu_busy_at_clock"] = busy
+                lines.append(f"- VALU busy at that clock: {busy:.3f} of the 1024 SIMDs' cycles "
+                             "(SQ_ACTIVE_INST_VALU x 4 / (1024 x duration x clock))")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"{args.name}.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")

@@ -143,6 +143,30 @@ def test_profile_calibration_is_the_first_copy(tmp_path):
     assert sorted(out["FETCH_SIZE"]) == [500.0, 520.0]
 
 
+def test_effective_clock_from_busy_cycles_and_the_trace(tmp_path):
+    # GRBM_GUI_ACTIVE counts busy cycles summed over the 8 XCDs: 8 x 2.0e9 x 1 ms of a 1 ms
+    # dispatch is a 2.0 GHz clock; the trace's dispatch ids pair the two files
+    from paper_1912_04791_amd import profsum
+    hdr = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id",'
+           '"Grid_Size","Kernel_Id","Kernel_Name","Workgroup_Size","LDS_Block_Size",'
+           '"Scratch_Size","VGPR_Count","Accum_VGPR_Count","SGPR_Count","Counter_Name",'
+           '"Counter_Value","Start_Timestamp","End_Timestamp"')
+    k = "dsve::k_step<3, 0, 0, false>"
+    rows = [hdr, f'5,5,"Agent 1",1,1,1,1,1,"{k}",256,0,0,4,0,32,"GRBM_GUI_ACTIVE",{8 * 2.0e9 * 1e-3},0,1',
+            f'5,5,"Agent 1",1,1,1,1,1,"{k}",256,0,0,4,0,32,"SQ_ACTIVE_INST_VALU",{0.5 * 1024 * 2.0e6 / 4},0,1',
+            f'6,6,"Agent 1",1,1,1,1,1,"{k}",256,0,0,4,0,32,"GRBM_GUI_ACTIVE",{8 * 1.9e9 * 2e-3},0,1']
+    (tmp_path / "run_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    thdr = '"Kind","Agent_Id","Queue_Id","Kernel_Id","Kernel_Name","Correlation_Id","Dispatch_Id","Start_Timestamp","End_Timestamp"'
+    trows = [thdr, f'"KERNEL_DISPATCH",1,1,1,"{k}",5,5,1000000,2000000',
+             f'"KERNEL_DISPATCH",1,1,1,"{k}",6,6,3000000,5000000',
+             f'"KERNEL_DISPATCH",1,1,1,"other",7,7,6000000,7000000']
+    (tmp_path / "run_kernel_trace.csv").write_text("\n".join(trows) + "\n")
+    got = profsum.clock_per_dispatch(str(tmp_path), "k_step<3, 0, 0, false>")
+    assert [round(c / 1e9, 6) for _, c, _ in got] == [2.0, 1.9]
+    d, f, c = got[0]
+    assert abs(c["SQ_ACTIVE_INST_VALU"] * 4 / (1024 * d * f) - 0.5) < 1e-12
+
+
 def test_more_than_one_gpu_is_refused_with_a_message():
     import subprocess
     import sys
