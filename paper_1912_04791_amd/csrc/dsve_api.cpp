@@ -185,6 +185,8 @@ static dsve_status build_tile_table(dsve_ctx *c, int tile)
     if (c->d_tile_chan && c->table_tile == tile) return DSVE_OK;
     const int64_t span = tile - 1;
     const int64_t nt = std::max<int64_t>(1, (c->n_edges - 1 + span - 1) / span);
+    // the step kernel indexes tiles in 32 bits (2^31 tiles of 63 cells are 3 TB of state)
+    if (nt >= ((int64_t)1 << 31)) return fail(c, DSVE_E_ARG, "too many tiles for this tile size");
     std::vector<int32_t> tab(nt);
     int64_t ch = 0;
     for (int64_t k = 0; k < nt; ++k) {

@@ -162,6 +162,7 @@ struct StepArgs {
     unsigned int *flags;
     int64_t n_edges;
     int64_t n_tiles;
+    int32_t tiles_lo, tiles_rem; // n_tiles / grid and n_tiles % grid (set at launch)
     int32_t n_channels;
     double g;
 };

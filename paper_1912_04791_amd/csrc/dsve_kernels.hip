@@ -177,37 +177,64 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
                                                                            const int32_t *__restrict__ TC,
                                                                            const unsigned long long *__restrict__ AM)
 {
-    extern __shared__ double s_dm[];          // [3][T]
+    extern __shared__ double s_dm_all[];      // [2][3][T]: D^- of even and odd tiles
     __shared__ unsigned long long s_acc;
     using Idx = typename StepIdx<WIDE>::type;
     const int T = blockDim.x;
     const int t = threadIdx.x;
-    unsigned long long reg_acc = 0ull;        // used by thread 0 only
-    int reg_chan = -1;
+    const int lane = t & 63;
 
-    // Software pipeline over the tiles of this workgroup: the channel of the tile two ahead and
-    // the edge offsets, first cell, length, boundary codes and CFL maximum of the next tile's
-    // home channel are loaded while the current tile computes, so a tile waits on one load
-    // (its state, with its channel record alongside) before it computes.  Lanes past the home
-    // channel's end find their channel by a forward scan and load its values directly.
-    const int64_t stride = gridDim.x;
-    int64_t k = blockIdx.x;
+    // Each workgroup takes a contiguous run of tiles, so consecutive tiles mostly share their
+    // home channel.  Every lane keeps the running CFL maximum of its cells in the channel the
+    // workgroup is collecting for (`acc_chan`, the home channel of its current tile) and the
+    // lanes are reduced across only when that channel changes, and at the end; cells of another
+    // channel (a tile that straddles a channel's end) go to their channel's slot at once.
+    //
+    // Software pipeline over the tiles: the channel of the tile two ahead and the edge offsets,
+    // first cell, length, boundary codes and CFL maximum of the next tile's home channel are
+    // loaded while the current tile computes, so a tile waits on one load (its state, with its
+    // channel record alongside) before it computes.  Lanes past the home channel's end find
+    // their channel by a forward scan and load its values directly.
+    // the tiles split evenly over the grid (lo or lo + 1 per workgroup, from the host); tile
+    // indices fit 32 bits (the host refuses 2^31 tiles)
+    const int wg = (int)blockIdx.x;
+    const int k_first = wg * A.tiles_lo + (wg < A.tiles_rem ? wg : A.tiles_rem);
+    const int k_end = k_first + A.tiles_lo + (wg < A.tiles_rem ? 1 : 0);
+    if (t == 0) s_acc = 0ull;
+    if (k_first >= k_end) return;   // the same for the whole workgroup
+    int k = k_first;
     // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
-    int nx_home = k < A.n_tiles ? TC[k] : 0;
-    int nx2_home = k + stride < A.n_tiles ? TC[k + stride] : 0;
+    int nx_home = TC[k];
+    int nx2_home = k + 1 < k_end ? TC[k + 1] : 0;
     Idx nx_eo0 = (Idx)EO[nx_home], nx_eo1 = (Idx)EO[nx_home + 1];
     int nx_bcl = CH[nx_home].bcl, nx_bcr = CH[nx_home].bcr;
     double nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
     // this workgroup's sub-slot of the CFL maxima it merges into (S is a power of two)
     unsigned long long *const amax_mine =
         A.amax_next + (int64_t)(blockIdx.x & (unsigned)(A.amax_split - 1)) * A.amax_stride;
-    for (; k < A.n_tiles; k += stride) {
+    int acc_chan = nx_home;
+    unsigned long long lane_acc = 0ull;
+    for (; k < k_end; ++k) {
         const int home = nx_home;
         const Idx eo0 = nx_eo0, eo1 = nx_eo1;
         const Idx h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
         const int h_bcl = nx_bcl, h_bcr = nx_bcr;
         const double am_home = nx_am;
-        if (t == 0) s_acc = 0ull;
+        if (home != acc_chan) {
+            // the workgroup moves on to another channel: merge what its lanes hold for the old
+            // one (two barriers, once per channel, not per tile)
+            const unsigned long long m = wave_max_u64(lane_acc);
+            if (lane == 0 && m != 0ull) atomicMax(&s_acc, m);
+            __syncthreads();
+            if (t == 0) {
+                if (s_acc != 0ull) flush_max(&amax_mine[acc_chan], s_acc);
+                s_acc = 0ull;
+            }
+            __syncthreads();
+            lane_acc = 0ull;
+            acc_chan = home;
+        }
+        double *const s_dm = s_dm_all + (int)(k & 1) * 3 * T;
         // lanes past the last edge (in the last tile only) compute the last edge again: their
         // results are never stored and no lane that updates a cell reads them
         const Idx ge_raw = (Idx)k * (Idx)(T - 1) + t;
@@ -246,9 +273,9 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         // the next tile's lookups go out after this tile's state loads and before its
         // arithmetic, so waiting for the state does not wait for them
         __builtin_amdgcn_sched_barrier(0);
-        if (k + stride < A.n_tiles) {
+        if (k + 1 < k_end) {
             nx_home = nx2_home;
-            nx2_home = k + 2 * stride < A.n_tiles ? TC[k + 2 * stride] : 0;
+            nx2_home = k + 2 < k_end ? TC[k + 2] : 0;
             nx_eo0 = (Idx)EO[nx_home];
             nx_eo1 = (Idx)EO[nx_home + 1];
             nx_bcl = CH[nx_home].bcl;
@@ -270,6 +297,9 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             }
             edge_fluct<G, PREC, CL>(hL, qL, zL, hRe, qRe, zRe, A.g, K, Dm, Dp, bad);
         }
+        // D^- goes to the left neighbour through this tile's half of the LDS buffer; the next
+        // tile writes the other half, so one barrier per tile orders every write after the
+        // reads of the tile before
         s_dm[t] = Dm[0];
         s_dm[T + t] = Dm[1];
         s_dm[2 * T + t] = Dm[2];
@@ -301,19 +331,15 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             }
         }
         raise_flag(A.flags, bad);
-        reduce_channel_max(sp_bits, c, upd, home, &s_acc, amax_mine);
-        __syncthreads();
-        if (t == 0) {
-            if (home != reg_chan) {
-                if (reg_chan >= 0) flush_max(&amax_mine[reg_chan], reg_acc);
-                reg_chan = home;
-                reg_acc = s_acc;
-            } else {
-                reg_acc = (s_acc > reg_acc) ? s_acc : reg_acc;
-            }
-        }
+        const bool mine = upd && c == acc_chan;
+        lane_acc = (mine && sp_bits > lane_acc) ? sp_bits : lane_acc;
+        const bool other = upd && c != acc_chan;
+        if (__ballot(other)) reduce_channel_max(sp_bits, c, other, -1, &s_acc, amax_mine);
     }
-    if (t == 0 && reg_chan >= 0) flush_max(&amax_mine[reg_chan], reg_acc);
+    const unsigned long long m = wave_max_u64(lane_acc);
+    if (lane == 0 && m != 0ull) atomicMax(&s_acc, m);
+    __syncthreads();
+    if (t == 0 && s_acc != 0ull) flush_max(&amax_mine[acc_chan], s_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,7 +673,7 @@ static hipError_t launch_fluct_prec(const FluctArgs &a, int G, int cl, hipStream
 template <int PREC, bool WIDE>
 static hipError_t launch_step_prec(const StepArgs &a, int G, int cl, int tile, int grid, hipStream_t s)
 {
-    const size_t lds = sizeof(double) * 3 * (size_t)tile;
+    const size_t lds = sizeof(double) * 6 * (size_t)tile;
 #define DSVE_LAUNCH_STEP(GG, CC) hipLaunchKernelGGL((k_step<GG, PREC, CC, WIDE>), dim3(grid), dim3(tile), lds, s, a, \
                                                    a.ch, a.eoff, a.tile_chan, a.amax_cur)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_LAUNCH_STEP)
@@ -658,7 +684,7 @@ static hipError_t launch_step_prec(const StepArgs &a, int G, int cl, int tile, i
 template <int PREC, bool WIDE>
 static hipError_t occupancy_query(int G, int cl, int tile, int &n)
 {
-    const size_t lds = sizeof(double) * 3 * (size_t)tile;
+    const size_t lds = sizeof(double) * 6 * (size_t)tile;
     hipError_t e = hipErrorInvalidValue;
 #define DSVE_OCC(GG, CC) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<GG, PREC, CC, WIDE>, tile, lds)
     DSVE_DISPATCH_G_CL(G, cl, DSVE_OCC)
@@ -696,8 +722,12 @@ hipError_t launch_step(const StepArgs &a, int precision, int G, int cl, int tile
                        hipStream_t stream)
 {
     if (tile < 64 || tile > kMaxTile || (tile & 63) || grid < 1) return hipErrorInvalidValue;
-    return step_needs_wide_index(a.n_edges) ? launch_step_w<true>(a, precision, G, cl, tile, grid, stream)
-                                            : launch_step_w<false>(a, precision, G, cl, tile, grid, stream);
+    // workgroup b takes tiles [b lo + min(b, rem), ...), lo + 1 of them for b < rem, else lo
+    StepArgs b = a;
+    b.tiles_lo = (int32_t)(a.n_tiles / grid);
+    b.tiles_rem = (int32_t)(a.n_tiles % grid);
+    return step_needs_wide_index(a.n_edges) ? launch_step_w<true>(b, precision, G, cl, tile, grid, stream)
+                                            : launch_step_w<false>(b, precision, G, cl, tile, grid, stream);
 }
 
 template <int PREC>
