@@ -184,56 +184,57 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
     const int t = threadIdx.x;
     const int lane = t & 63;
 
-    // Each workgroup takes a contiguous run of tiles, so consecutive tiles mostly share their
-    // home channel.  Every lane keeps the running CFL maximum of its cells in the channel the
-    // workgroup is collecting for (`acc_chan`, the home channel of its current tile) and the
-    // lanes are reduced across only when that channel changes, and at the end; cells of another
-    // channel (a tile that straddles a channel's end) go to their channel's slot at once.
-    //
-    // Software pipeline over the tiles: the channel of the tile two ahead and the edge offsets,
-    // first cell, length, boundary codes and CFL maximum of the next tile's home channel are
-    // loaded while the current tile computes, so a tile waits on one load (its state, with its
-    // channel record alongside) before it computes.  Lanes past the home channel's end find
-    // their channel by a forward scan and load its values directly.
-    // the tiles split evenly over the grid (lo or lo + 1 per workgroup, from the host); tile
-    // indices fit 32 bits (the host refuses 2^31 tiles)
+    // Each workgroup takes a contiguous run of tiles (the tiles split evenly over the grid: lo or
+    // lo + 1 per workgroup, from the host; tile indices fit 32 bits, the host refuses 2^31
+    // tiles), so consecutive tiles mostly share their home channel, the channel of the tile's
+    // first edge.  The home channel's values (edge offsets, boundary codes, CFL maximum of W^n,
+    // time step) are loaded when the run enters the channel, and every lane keeps the running
+    // CFL maximum of its cells in it; the lanes are reduced across only when the run leaves the
+    // channel, and at the end.  Cells of another channel (a tile that straddles a channel's
+    // end) find their channel by a forward scan and go to its slot at once.
     const int wg = (int)blockIdx.x;
     const int k_first = wg * A.tiles_lo + (wg < A.tiles_rem ? wg : A.tiles_rem);
     const int k_end = k_first + A.tiles_lo + (wg < A.tiles_rem ? 1 : 0);
     if (t == 0) s_acc = 0ull;
     if (k_first >= k_end) return;   // the same for the whole workgroup
-    int k = k_first;
-    // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
-    int nx_home = TC[k];
-    int nx2_home = k + 1 < k_end ? TC[k + 1] : 0;
-    Idx nx_eo0 = (Idx)EO[nx_home], nx_eo1 = (Idx)EO[nx_home + 1];
-    int nx_bcl = CH[nx_home].bcl, nx_bcr = CH[nx_home].bcr;
-    double nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
     // this workgroup's sub-slot of the CFL maxima it merges into (S is a power of two)
     unsigned long long *const amax_mine =
         A.amax_next + (int64_t)(blockIdx.x & (unsigned)(A.amax_split - 1)) * A.amax_stride;
-    int acc_chan = nx_home;
+    int home = -1;
+    Idx eo0 = 0, eo1 = 0;
+    int h_bcl = 0, h_bcr = 0;
+    double am_home = 0.0, dt_home = 0.0, r_home = 0.0;
     unsigned long long lane_acc = 0ull;
-    for (; k < k_end; ++k) {
-        const int home = nx_home;
-        const Idx eo0 = nx_eo0, eo1 = nx_eo1;
-        const Idx h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
-        const int h_bcl = nx_bcl, h_bcr = nx_bcr;
-        const double am_home = nx_am;
-        if (home != acc_chan) {
-            // the workgroup moves on to another channel: merge what its lanes hold for the old
-            // one (two barriers, once per channel, not per tile)
-            const unsigned long long m = wave_max_u64(lane_acc);
-            if (lane == 0 && m != 0ull) atomicMax(&s_acc, m);
-            __syncthreads();
-            if (t == 0) {
-                if (s_acc != 0ull) flush_max(&amax_mine[acc_chan], s_acc);
-                s_acc = 0ull;
+    int nx_home = TC[k_first];
+    for (int k = k_first; k < k_end; ++k) {
+        const int tile_home = nx_home;
+        if (k + 1 < k_end) nx_home = TC[k + 1];
+        if (tile_home != home) {
+            if (home >= 0) {
+                // merge what the lanes hold for the channel the run leaves (two barriers, once
+                // per channel, not per tile)
+                const unsigned long long m = wave_max_u64(lane_acc);
+                if (lane == 0 && m != 0ull) atomicMax(&s_acc, m);
+                __syncthreads();
+                if (t == 0) {
+                    if (s_acc != 0ull) flush_max(&amax_mine[home], s_acc);
+                    s_acc = 0ull;
+                }
+                __syncthreads();
+                lane_acc = 0ull;
             }
-            __syncthreads();
-            lane_acc = 0ull;
-            acc_chan = home;
+            // (a channel's first cell and length follow from its edge offsets: eoff[c] = off[c] + c)
+            home = tile_home;
+            eo0 = (Idx)EO[home];
+            eo1 = (Idx)EO[home + 1];
+            h_bcl = CH[home].bcl;
+            h_bcr = CH[home].bcr;
+            am_home = amax_of(AM, home, A.amax_stride, A.amax_split);
+            // dt = CFL dx / amax and dt/dx, as every lane of another channel computes them
+            dt_home = CH[home].cfl_dx * rcp_h(am_home);
+            r_home = dt_home * CH[home].inv_dx;
         }
+        const Idx h_cell0 = eo0 - home, h_ncell = eo1 - eo0 - 1;
         double *const s_dm = s_dm_all + (int)(k & 1) * 3 * T;
         // lanes past the last edge (in the last tile only) compute the last edge again: their
         // results are never stored and no lane that updates a cell reads them
@@ -270,20 +271,6 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const double hR = ldx<WIDE>(A.h, ir);
         const double qR = ldx<WIDE>(A.q, ir);
         const double zR = ldx<WIDE>(A.z, ir);
-        // the next tile's lookups go out after this tile's state loads and before its
-        // arithmetic, so waiting for the state does not wait for them
-        __builtin_amdgcn_sched_barrier(0);
-        if (k + 1 < k_end) {
-            nx_home = nx2_home;
-            nx2_home = k + 2 < k_end ? TC[k + 2] : 0;
-            nx_eo0 = (Idx)EO[nx_home];
-            nx_eo1 = (Idx)EO[nx_home + 1];
-            nx_bcl = CH[nx_home].bcl;
-            nx_bcr = CH[nx_home].bcr;
-            // the CFL maximum of W^n is fixed during the step: reuse it within a channel
-            if (nx_home != home) nx_am = amax_of(AM, nx_home, A.amax_stride, A.amax_split);
-        }
-        __builtin_amdgcn_sched_barrier(0);
         {
             double hRe = hR, qRe = qR, zRe = zR;
             if (e == 0) {
@@ -307,9 +294,11 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
         const bool upd = have_edge && (t < T - 1) && (e < ncell);
         unsigned long long sp_bits = 0ull;
         if (upd) {
-            const double amax = c == home ? am_home : amax_of(AM, c, A.amax_stride, A.amax_split);
-            const double dt = ci.cfl_dx * rcp_h(amax);
-            const double r = dt * ci.inv_dx;
+            double dt = dt_home, r = r_home;
+            if (c != home) {
+                dt = ci.cfl_dx * rcp_h(amax_of(AM, c, A.amax_stride, A.amax_split));
+                r = dt * ci.inv_dx;
+            }
             const Idx i = cell0 + e;
             // W_i^{n+1} = W_i^n - dt/dx (D^-_{i+1/2} + D^+_{i-1/2}) + dt S(W_i^n)
             // (Sec. 3, Eq. scheme; S from the friction slope when K_s is given)
@@ -331,15 +320,15 @@ __global__ __launch_bounds__(kMaxTile, step_min_waves(PREC, CL)) void k_step(Ste
             }
         }
         raise_flag(A.flags, bad);
-        const bool mine = upd && c == acc_chan;
+        const bool mine = upd && c == home;
         lane_acc = (mine && sp_bits > lane_acc) ? sp_bits : lane_acc;
-        const bool other = upd && c != acc_chan;
+        const bool other = upd && c != home;
         if (__ballot(other)) reduce_channel_max(sp_bits, c, other, -1, &s_acc, amax_mine);
     }
     const unsigned long long m = wave_max_u64(lane_acc);
     if (lane == 0 && m != 0ull) atomicMax(&s_acc, m);
     __syncthreads();
-    if (t == 0 && s_acc != 0ull) flush_max(&amax_mine[acc_chan], s_acc);
+    if (t == 0 && s_acc != 0ull) flush_max(&amax_mine[home], s_acc);
 }
 
 // ---------------------------------------------------------------------------
