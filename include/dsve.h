@@ -274,7 +274,9 @@ dsve_status dsve_clear_error(dsve_ctx *ctx);
  *   tile           threads (= edges) per workgroup: 64, 128, 192 or 256
  *   blocks_per_cu  persistent workgroups per compute unit (1..1024); 0 = as many
  *                  as fit on a compute unit at once (occupancy of the kernel); more than
- *                  fit oversubscribes the grid (workgroups start as others finish)
+ *                  fit oversubscribes the grid (workgroups start as others finish).  The
+ *                  grid is capped at one workgroup per tile, and each workgroup takes an
+ *                  even contiguous run of the tiles
  *   graph_steps    steps per captured HIP graph: a multiple of 6 in [6, 600],
  *                  or 0 to launch every step directly
  * The results do not depend on these (each edge and cell is computed the same
@@ -285,7 +287,8 @@ dsve_status dsve_get_launch(const dsve_ctx *ctx, int *tile, int *blocks_per_cu, 
 /* CFL sub-slots of the fused step kernel: each workgroup merges its partial
  * CFL maximum with an atomic into one of `split` sub-slots per channel (1, 2 or
  * 4; 0, the default, picks 4 when many workgroups share a channel and each
- * merges after a few tiles, else 1), and every tile reads the maximum over them.
+ * merges after a few tiles, else 1), and a workgroup reads the maximum over them
+ * when its run of tiles enters a channel.
  * More sub-slots spread the atomics of a step over more addresses; fewer keep
  * the read to fewer loads.  The results do not depend on it.  The getter reports
  * the count in effect for the current launch configuration. */
