@@ -211,6 +211,33 @@ def test_launch_configuration_does_not_change_bits(torch_dev, dsve):
             assert np.array_equal(a, b)
 
 
+def test_tile_runs_across_many_short_channels(torch_dev, dsve):
+    # the per-step kernel (resident runs off) on 300 channels of 1-90 cells: a workgroup's run of
+    # tiles crosses many channels, and a tile holds several whole channels; every launch gives the
+    # same bits (runs of one tile per workgroup up to runs of hundreds) and matches the oracle
+    wl = inputs.make_c4(n_channels=300, len_lo=1, len_hi=90, steps=23)
+    outs = []
+    for precision in ("fp64", "mixed"):
+        runs = []
+        for launch in [(64, 1, 0), (64, 3, 6), (256, 1, 0), (128, 7, 12), (64, 128, 6), (192, 2, 0)]:
+            ctx = dsve.Context.from_workload(wl, precision=precision)
+            ctx.set_resident(0)
+            ctx.set_launch(*launch)
+            h, q, z, t = dsve.upload(wl)
+            ctx.adot_step(h, q, z, wl.steps, t)
+            ctx.sync()
+            runs.append(tuple(x.cpu().numpy() for x in (h, q, z, t)))
+            ctx.close()
+        for o in runs[1:]:
+            for a, b in zip(o, runs[0]):
+                assert np.array_equal(a, b)
+        outs.append(runs[0])
+    ref = oracle_run(wl)
+    for got, tol in zip(outs, (TOL, 1e-5)):
+        per = per_channel_rel_l1(got, ref, wl.offsets)
+        assert per.max() <= tol, per.max()
+
+
 def test_cfl_sub_slots_do_not_change_bits(torch_dev, dsve):
     # the per-channel CFL maximum merged into 1, 2 or 4 sub-slots, with one tile per
     # workgroup and with persistent workgroups, single channel and batched
