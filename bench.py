@@ -276,10 +276,14 @@ def gpu_state_after(wl, precision: str, steps: int, cells=None, tune_cache: str 
     return out, ms / max(steps, 1)
 
 
-def rel_l1_max(got, ref) -> float:
-    hs = np.abs(ref[0]).sum()
-    return float(max(np.abs(g - r).sum() / max(np.abs(r).sum(), 1e-3 * hs)
-                     for g, r in zip(got, ref)))
+def rel_l1_max(got, ref, g: float = 9.81) -> float:
+    """Largest relative L1 over h, q, z: ||got - ref||_1 / max(||ref||_1, 1e-3 ||s||_1), s the
+    variable's natural size in its units (the depth for h and z, the critical discharge
+    h sqrt(g h) for q)."""
+    h = np.abs(ref[0])
+    scales = (h, h * np.sqrt(g * h), h)
+    return float(max(np.abs(a - r).sum() / max(np.abs(r).sum(), 1e-3 * s.sum())
+                     for a, r, s in zip(got, ref, scales)))
 
 
 # Algorithmic figures of the standalone entry points: operations per unit as counted for the step

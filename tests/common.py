@@ -26,15 +26,24 @@ def oracle_run(wl: inputs.Workload, steps: int | None = None, nthreads: int | No
     return oracle.run_batched(specs, wl.offsets, wl.h, wl.q, wl.z, n, nthreads=nthreads)
 
 
-def rel_l1(a: np.ndarray, ref: np.ndarray, h_ref: np.ndarray) -> float:
-    """||a - ref||_1 / max(||ref||_1, 1e-3 ||h_ref||_1) (per variable)."""
-    den = max(np.abs(ref).sum(), 1e-3 * np.abs(h_ref).sum())
+def rel_l1(a: np.ndarray, ref: np.ndarray, scale: np.ndarray) -> float:
+    """||a - ref||_1 / max(||ref||_1, 1e-3 ||scale||_1) (per variable; `scale` is the variable's
+    natural size in its own units, see l1_scales)."""
+    den = max(np.abs(ref).sum(), 1e-3 * np.abs(scale).sum())
     return float(np.abs(a - ref).sum() / den)
+
+
+def l1_scales(h_ref: np.ndarray, g: float = inputs.G_ACC):
+    """Scales of the floor of the relative L1 for h, q, z: the depth for h and z, and for q the
+    critical discharge h c = h sqrt(g h) (q / (h c) is the Froude number, the non-dimensional
+    discharge of Sec. 3.3)."""
+    h = np.abs(h_ref)
+    return h, h * np.sqrt(g * h), h
 
 
 def max_rel_l1(got, ref) -> float:
     """Largest relative L1 error over h, q, z."""
-    return max(rel_l1(g, r, ref[0]) for g, r in zip(got[:3], ref[:3]))
+    return max(rel_l1(g, r, s) for g, r, s in zip(got[:3], ref[:3], l1_scales(ref[0])))
 
 
 def per_channel_rel_l1(got, ref, offsets) -> np.ndarray:
@@ -42,5 +51,6 @@ def per_channel_rel_l1(got, ref, offsets) -> np.ndarray:
     out = np.zeros(C)
     for c in range(C):
         lo, hi = offsets[c], offsets[c + 1]
-        out[c] = max(rel_l1(g[lo:hi], r[lo:hi], ref[0][lo:hi]) for g, r in zip(got[:3], ref[:3]))
+        out[c] = max(rel_l1(g[lo:hi], r[lo:hi], s)
+                     for g, r, s in zip(got[:3], ref[:3], l1_scales(ref[0][lo:hi])))
     return out
