@@ -33,12 +33,19 @@
 // The fluctuation (Sec. 3.1, Eq. DOTjumpN) is accumulated as
 //   S_A = sum_k w_k A(Psi_k) dW   with the explicit flux matrix (Eq. W&A_definition):
 //         A dW = [dq, c^2 ((1 - Fr^2) dh + 2Fr dq/c + dz), b c (dq/c - kappa Fr dh)],
+// and, in FP64,
 //   D^- = sum_k w_k A^-(Psi_k) dW,  D^+ = S_A - D^-,
 // where A^- = (A - |A|)/2 (Eqs. asbA, ExAbsA) is the sum of c mu_m r_m l_m over the negative
 // eigenvalues.  The root labelled 3 below is always the middle one, so at most one root differs
 // in sign from it, and A^- takes one eigenpair o: A^- dW = c min(mu_o, 0) (l_o . dW) r_o when
 // mu_3 >= 0 (o the smallest root), A^- dW = A dW - c max(mu_o, 0) (l_o . dW) r_o when mu_3 < 0
 // (o the largest).  So |A| is never formed, and R^-1 dW is needed for one row only.
+// The mixed form sums in FP32
+//   S_B = sum_k w_k |A(Psi_k)| dW  with |A| dW = sum_m c |mu_m| (l_m . dW) r_m,
+//   D^- = (S_A - S_B)/2,  D^+ = (S_A + S_B)/2,
+// whose rounding is spread evenly over D^- and D^+ (with one eigenpair, FP32 rounding lands on
+// whichever of the two is formed as a difference, and long runs through stagnant flow drift
+// further from FP64).
 //
 // Arithmetic kernels (own implementations of published methods):
 //   rcp_h / rsqrt_h: hardware reciprocal / reciprocal-square-root estimate (about 2^-24
@@ -48,8 +55,9 @@
 //     polynomial in 1 - a (FP32) and two Newton steps on the trisection cubic 4C^3 - 3C = a
 //     (FP64), the sine from sin(3 theta) = S (4C^2 - 1), i.e. S = sqrt(1 - a^2) / (4C^2 - 1),
 //     with 4C^2 - 1 in [2, 3].  The roots at -x are those at x negated, so the eigenvalues are
-//     sign(x) {C, -P, -Q} about f, P, Q = C/2 +- (sqrt3/2) S, labelled in that order, not sorted:
-//     every sum over the three eigenpairs is symmetric in the labels.
+//     sign(x) {C, -P, -Q} about f, P, Q = C/2 +- (sqrt3/2) S, labelled in that order, not
+//     sorted (a sum over the three eigenpairs is symmetric in the labels); since P >= Q >= 0,
+//     mu_3 is the middle root, and mu_2 the smallest for x >= 0 and the largest for x < 0.
 //   Gap product: (mu_2 - mu_1)(mu_3 - mu_1)(mu_3 - mu_2) = (3 sqrt3 / 4) m^3 sin(3 theta)
 //     = (2 sqrt3 / 9) k1^(3/2) sin(phi), so its reciprocal is (3 sqrt3 / 2) k1^(-3/2) / sin(phi),
 //     from the k1^(-1/2) and 1/sin(phi) the roots already need.
@@ -278,8 +286,8 @@ __device__ __forceinline__ void third_angle(float a, float y, float &C, float &S
 struct Eig64 {
     double Fr, c, inv_c, b, kFr;
     double mu1, mu2, mu3;
-    double g31, g32;        // mu_3 - mu_1, mu_3 - mu_2
-    double inv_gp;          // 1 / ((mu_2 - mu_1) (mu_3 - mu_1) (mu_3 - mu_2))
+    double g21, g31, g32;   // mu_2 - mu_1, mu_3 - mu_1, mu_3 - mu_2
+    double inv_gp;          // 1 / (g21 g31 g32)
     double ms;              // sign(x) m: the smallest root is mu_2 when ms >= 0, mu_1 otherwise
 };
 
@@ -349,10 +357,11 @@ __device__ __forceinline__ void eig64(double h, double q, double g, const Closur
     E.mu1 = fma(ms, C, f);
     E.mu2 = fma(-ms, fma(0.5, C, r), f);
     E.mu3 = fma(-ms, fma(0.5, C, -r), f);
+    E.g21 = -ms * fma(1.5, C, r);    // mu2 - mu1 = -ms (P + C)
     E.g31 = -ms * fma(1.5, C, -r);   // mu3 - mu1 = -ms (Q + C)
     E.g32 = (2.0 * ms) * r;          // mu3 - mu2 = ms (P - Q)
     E.ms = ms;
-    // 1 / ((mu2 - mu1) g31 g32): the gap product is sign(x) (3 sqrt3 / 4) m^3 sin(phi)
+    // 1 / (g21 g31 g32): the gap product is sign(x) (3 sqrt3 / 4) m^3 sin(phi)
     E.inv_gp = (copysign(kInvGapScale, x) * r13) * inv_y;
 }
 
@@ -386,6 +395,40 @@ __device__ __forceinline__ double speed64(double h, double q, double g, const Cl
     return (a.gh * a.inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
 }
 
+// Accumulate one quadrature node: SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node,
+// and the weights sum to one, so the caller takes sum_k w_k dq = dq), SB += w |A| dW.
+__device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, double dh, double dq,
+                                                  double dz, double SA[3], double SB[3])
+{
+    const double Fr = E.Fr, c = E.c;
+    const double mu1 = E.mu1, mu2 = E.mu2, mu3 = E.mu3;
+    const double dqn = dq * E.inv_c;
+    const double base = fma(-Fr, Fr, 1.0);   // (c^2 - u^2) / c^2
+    // explicit A dW (row 0 is dq)
+    const double A1n = fma(base, dh, fma(2.0 * Fr, dqn, dz));
+    const double A2n = E.b * fma(-E.kFr, dh, dqn);
+    // numerators of l_i . dW (non-dimensional)
+    const double n1 = fma(fma(mu2, mu3, base), dh, fma(mu1, dqn, dz));
+    const double n2 = fma(fma(mu3, mu1, base), dh, fma(mu2, dqn, dz));
+    const double n3 = fma(fma(mu1, mu2, base), dh, fma(mu3, dqn, dz));
+    // |mu_i| (l_i . dW) up to the common factor 1/P of the denominators 1/d_1 = g32/P,
+    // 1/d_2 = -g31/P, 1/d_3 = g21/P, which enters once per row with w and c or c^2
+    const double b1 = n1 * (fabs(mu1) * E.g32);
+    const double b2 = -n2 * (fabs(mu2) * E.g31);
+    const double b3 = n3 * (fabs(mu3) * E.g21);
+    const double e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
+    const double B0 = b1 + b2 + b3;
+    const double B1 = fma(b1, mu1, fma(b2, mu2, b3 * mu3));
+    const double B2 = fma(b1, fma(e1, e1, -1.0), fma(b2, fma(e2, e2, -1.0), b3 * fma(e3, e3, -1.0)));
+    const double wc = w * c, wcc = wc * c;
+    const double wcP = wc * E.inv_gp, wccP = wcc * E.inv_gp;
+    SA[1] = fma(wcc, A1n, SA[1]);
+    SA[2] = fma(wc, A2n, SA[2]);
+    SB[0] = fma(wcP, B0, SB[0]);
+    SB[1] = fma(wccP, B1, SB[1]);
+    SB[2] = fma(wcP, B2, SB[2]);
+}
+
 // Paths of a quadrature node through D^-: with every lane's mu_3 >= 0 and ms >= 0 (flow towards
 // +x below |Fr| of about 3 under weak transport), o = 2 and D^- takes min(mu_2, 0); with every
 // lane's mu_3 < 0 and ms < 0 (the mirror case), o = 2 and D^- takes A dW - max(mu_2, 0); any
@@ -396,15 +439,14 @@ enum { NODE_PER_LANE = 0, NODE_UP = 1, NODE_DOWN = 2 };
 // mu_3 < 0, Wt = sum of w over the latter (row 0 of A dW is dq at every node), SD = the
 // projection terms of D^-.  Then D^- = (dq Wt, S2) + SD and D^+ = (dq, S1 + S2) - D^-; the
 // weights sum to one, so row 0 of S_A is dq.
-template <typename T>
 struct NodeSums {
-    T S1[3], S2[3], SD[3];
+    double S1[3], S2[3], SD[3];
     double Wt;
 };
 
-template <int PATH, typename T>
+template <int PATH>
 __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh, double dq, double dz,
-                                             NodeSums<T> &N)
+                                             NodeSums &N)
 {
     // One body for the three paths, so that a lane's arithmetic does not depend on the path its
     // wave takes: the uniform paths fix `up` and `two`, and their selects fold away.
@@ -429,12 +471,12 @@ __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh
     const double eo = Fr - mo;
     const double wc = w * c, wcc = wc * c;
     const double pb = (wc * E.inv_gp) * bo;   // w c to (l_o . dW): r_o = [1, c mu_o, (Fr - mu_o)^2 - 1]
-    N.SD[0] = (T)((double)N.SD[0] + pb);
-    N.SD[1] = (T)fma(pb, c * mo, (double)N.SD[1]);
-    N.SD[2] = (T)fma(pb, fma(eo, eo, -1.0), (double)N.SD[2]);
+    N.SD[0] += pb;
+    N.SD[1] = fma(pb, c * mo, N.SD[1]);
+    N.SD[2] = fma(pb, fma(eo, eo, -1.0), N.SD[2]);
     // w A dW into S1 (mu_3 >= 0) or S2 (mu_3 < 0, with its weight)
-    const T a1 = (T)fma(wcc, A1n, (double)(up ? N.S1[1] : N.S2[1]));
-    const T a2 = (T)fma(wc, A2n, (double)(up ? N.S1[2] : N.S2[2]));
+    const double a1 = fma(wcc, A1n, up ? N.S1[1] : N.S2[1]);
+    const double a2 = fma(wc, A2n, up ? N.S1[2] : N.S2[2]);
     N.S1[1] = up ? a1 : N.S1[1];
     N.S1[2] = up ? a2 : N.S1[2];
     N.S2[1] = up ? N.S2[1] : a1;
@@ -442,17 +484,16 @@ __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh
     N.Wt = up ? N.Wt : N.Wt + w;
 }
 
-// D^- and D^+ of an edge from its node sums (row 0 in FP64 from dq; D^- + D^+ = dq in row 0).
-template <typename T>
-__device__ __forceinline__ void node_sums_to_fluct(const NodeSums<T> &N, double dq, double Dm[3],
+// D^- and D^+ of an edge from its node sums (D^- + D^+ = dq in row 0).
+__device__ __forceinline__ void node_sums_to_fluct(const NodeSums &N, double dq, double Dm[3],
                                                    double Dp[3])
 {
-    Dm[0] = fma(dq, N.Wt, (double)N.SD[0]);
+    Dm[0] = fma(dq, N.Wt, N.SD[0]);
     Dp[0] = dq - Dm[0];
 #pragma unroll
     for (int r = 1; r < 3; ++r) {
-        Dm[r] = (double)N.S2[r] + (double)N.SD[r];
-        Dp[r] = (double)N.S1[r] - (double)N.SD[r];
+        Dm[r] = N.S2[r] + N.SD[r];
+        Dp[r] = N.S1[r] - N.SD[r];
     }
 }
 
@@ -464,7 +505,7 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
                                         double Dp[3], unsigned &bad)
 {
     const double dh = hR - hL, dq = qR - qL, dz = zR - zL;
-    NodeSums<double> N = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, 0.0};
+    NodeSums N = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, 0.0};
     unsigned long long xmax = 0ull;
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
@@ -489,9 +530,8 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
 struct EigF {
     float Fr, c, inv_c, b, kFr;
     float mu1, mu2, mu3;
-    float g31, g32;
+    float g21, g31, g32;
     float inv_gp;
-    float ms;
 };
 
 // Returns false when the node must be evaluated in FP64 (the FP32 argument only selects
@@ -531,46 +571,41 @@ __device__ __forceinline__ bool eigf(float h, float q, float g, const Closure &K
     E.mu1 = fmaf(ms, C, f);
     E.mu2 = fmaf(-ms, fmaf(0.5f, C, r), f);
     E.mu3 = fmaf(-ms, Q, f);
+    E.g21 = -ms * fmaf(1.5f, C, r);
     E.g31 = -ms * (C + Q);
     E.g32 = (2.0f * ms) * r;
     E.inv_gp = (copysignf((float)kInvGapScale, x) * r13) * inv_y;
-    E.ms = ms;
     return true;
 }
 
-// One FP32 node into the sums of D^- (the sums and the eigenpair o of node_minus64, chosen per
-// lane: in the mixed form the wave-uniform paths cost more in branches than they save).
-// eta = dh + dz (rounded from FP64): (1 - Fr^2) dh + dz = eta - Fr^2 dh keeps a still free
-// surface (eta = 0, Fr = 0) exact.
-__device__ __forceinline__ void node_minusf(const EigF &E, float w, double w64, float dh, float dq,
-                                            float eta, NodeSums<float> &N)
+// One FP32 node: SA += w A dW (rows 1, 2), SB += w |A| dW.  eta = dh + dz (rounded from FP64):
+// (1 - Fr^2) dh + dz = eta - Fr^2 dh keeps a still free surface (eta = 0, Fr = 0) exact.
+__device__ __forceinline__ void node_accumulatef(const EigF &E, float w, float dh, float dq, float eta,
+                                                 float SA[3], float SB[3])
 {
-    const bool up = E.mu3 >= 0.0f;
-    const bool two = up == (E.ms >= 0.0f);
     const float Fr = E.Fr, c = E.c;
+    const float mu1 = E.mu1, mu2 = E.mu2, mu3 = E.mu3;
     const float dqn = dq * E.inv_c;
     const float nF2 = -Fr * Fr;
     const float A1n = fmaf(nF2, dh, fmaf(2.0f * Fr, dqn, eta));
     const float A2n = E.b * fmaf(-E.kFr, dh, dqn);
-    const float mo = two ? E.mu2 : E.mu1;
-    const float mx = two ? E.mu1 : E.mu2;
-    const float gd = two ? -E.g31 : E.g32;
-    const float to = fminf(up ? mo : -mo, 0.0f);
-    const float no = fmaf(fmaf(E.mu3, mx, nF2), dh, fmaf(mo, dqn, eta));
-    const float bo = no * (to * gd);
-    const float eo = Fr - mo;
+    const float n1 = fmaf(fmaf(mu2, mu3, nF2), dh, fmaf(mu1, dqn, eta));
+    const float n2 = fmaf(fmaf(mu3, mu1, nF2), dh, fmaf(mu2, dqn, eta));
+    const float n3 = fmaf(fmaf(mu1, mu2, nF2), dh, fmaf(mu3, dqn, eta));
+    const float b1 = n1 * (fabsf(mu1) * E.g32);
+    const float b2 = -n2 * (fabsf(mu2) * E.g31);
+    const float b3 = n3 * (fabsf(mu3) * E.g21);
+    const float e1 = Fr - mu1, e2 = Fr - mu2, e3 = Fr - mu3;
+    const float B0 = b1 + b2 + b3;
+    const float B1 = fmaf(b1, mu1, fmaf(b2, mu2, b3 * mu3));
+    const float B2 = fmaf(b1, fmaf(e1, e1, -1.0f), fmaf(b2, fmaf(e2, e2, -1.0f), b3 * fmaf(e3, e3, -1.0f)));
     const float wc = w * c, wcc = wc * c;
-    const float pb = (wc * E.inv_gp) * bo;
-    N.SD[0] = N.SD[0] + pb;
-    N.SD[1] = fmaf(pb, c * mo, N.SD[1]);
-    N.SD[2] = fmaf(pb, fmaf(eo, eo, -1.0f), N.SD[2]);
-    const float a1 = fmaf(wcc, A1n, up ? N.S1[1] : N.S2[1]);
-    const float a2 = fmaf(wc, A2n, up ? N.S1[2] : N.S2[2]);
-    N.S1[1] = up ? a1 : N.S1[1];
-    N.S1[2] = up ? a2 : N.S1[2];
-    N.S2[1] = up ? N.S2[1] : a1;
-    N.S2[2] = up ? N.S2[2] : a2;
-    N.Wt = up ? N.Wt : N.Wt + w64;
+    const float wcP = wc * E.inv_gp, wccP = wcc * E.inv_gp;
+    SA[1] = fmaf(wcc, A1n, SA[1]);
+    SA[2] = fmaf(wc, A2n, SA[2]);
+    SB[0] = fmaf(wcP, B0, SB[0]);
+    SB[1] = fmaf(wccP, B1, SB[1]);
+    SB[2] = fmaf(wcP, B2, SB[2]);
 }
 
 template <int G, int CL>
@@ -584,24 +619,34 @@ __device__ __forceinline__ void fluct_mixed(double hL, double qL, double zL, dou
     const float gf = (float)g;
     // the node sums in FP32 (row 0 of S_A is dq, in FP64); a node in the band is evaluated in FP64
     // and its terms, which no longer carry the FP32 error near coalescence, are added rounded
-    NodeSums<float> N = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.0};
+    float SA[3] = {0.f, 0.f, 0.f}, SB[3] = {0.f, 0.f, 0.f};
     unsigned long long xmax = 0ull;
     DSVE_UNROLL(DSVE_NODE_UNROLL)
     for (int k = 0; k < G; ++k) {
         const float sf = (float)Gauss<G>::s[k];
-        const double w = Gauss<G>::w[k];
         EigF E;
         if (eigf<CL>(fmaf(sf, dhf, hLf), fmaf(sf, dqf, qLf), gf, K, E)) {
-            node_minusf(E, (float)w, w, dhf, dqf, etaf, N);
+            node_accumulatef(E, (float)Gauss<G>::w[k], dhf, dqf, etaf, SA, SB);
         } else {
             const double s = Gauss<G>::s[k];
             Eig64 E64;
             eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E64, xmax);
-            node_minus64<NODE_PER_LANE>(E64, w, dh, dq, dz, N);
+            double NA[3] = {0.0, 0.0, 0.0}, NB[3] = {0.0, 0.0, 0.0};
+            node_accumulate64(E64, Gauss<G>::w[k], dh, dq, dz, NA, NB);
+            SA[1] += (float)NA[1];
+            SA[2] += (float)NA[2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) SB[r] += (float)NB[r];
         }
     }
     bad |= arg_flags(xmax, true);
-    node_sums_to_fluct(N, dq, Dm, Dp);
+    const double A[3] = {dq, (double)SA[1], (double)SA[2]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double B = (double)SB[r];
+        Dm[r] = 0.5 * (A[r] - B);
+        Dp[r] = 0.5 * (A[r] + B);
+    }
 }
 
 // CFL speed in FP32 for the mixed form (the largest root at |Fr|, as speed64); the FP64 speed

@@ -1,9 +1,8 @@
 """Host model of the mixed form's FP32 node arithmetic (test infrastructure).
 
 Evaluates, with numpy, the FP32 eigenstructure and node accumulation the mixed-form kernels
-run at each quadrature node (the closed form of Sec. 3.3 in Froude-number variables, and
-A^- dW = ((A - |A|)/2) dW of Eqs. asbA, ExAbsA from the one eigenpair whose eigenvalue differs in
-sign from the middle one), so that the rounding error of FP32 near coalescing
+run at each quadrature node (the closed form of Sec. 3.3 in Froude-number variables, the
+matrix-vector |A| dW of Eqs. asbA, ExAbsA), so that the rounding error of FP32 near coalescing
 eigenvalues can be studied on the CPU: with every node in FP32 ("band off"), which no kernel
 runs, and with the nodes whose arccos argument lies within the FP64 band taken from the FP64
 oracle instead.
@@ -71,14 +70,12 @@ def cos_third_acos_f32(a):
     return p
 
 
-def node_terms(h, q, dh, dq, eta, w, g, kqg, band, sums):
-    """One quadrature node of the mixed form (Grass law in closed form, kappa = 1), added to the
-    running FP32 sums of D^- (`sums`: S1, S2 rows 1-2, SD rows 0-2, Wt in float64): the eigenpair
-    o of the root labelled 1 or 2 that differs in sign from the middle root mu_3, per edge, as
-    the kernels take it.  Returns a mask of the nodes whose arccos argument lies within `band` of
-    +-1 (band = 0: none)."""
+def node_terms(h, q, dh, dq, eta, w, g, kqg, band):
+    """One quadrature node of the mixed form (Grass law in closed form, kappa = 1): returns the
+    node's contributions w A dW (rows 1, 2) and w |A| dW (rows 0..2) in FP32, and a mask of the
+    nodes whose arccos argument lies within `band` of +-1 (band = 0: none)."""
     h, q, dh, dq, eta = (_r(v) for v in (h, q, dh, dq, eta))
-    g, wf = f32(g), f32(w)
+    g, w = f32(g), f32(w)
     K1, K2 = f32(1.0 + 3.0 * kqg), f32(2.0 + 9.0 * kqg)
     gh = mul(g, h)
     t = _r(1.0 / np.sqrt(mul(mul(gh, h), h).astype(np.float64)))
@@ -102,13 +99,14 @@ def node_terms(h, q, dh, dq, eta, w, g, kqg, band, sums):
     f = mul(f32(2.0 / 3.0), Fr)
     rr = mul(f32(0.86602540378443864676), S)
     c = mul(gh, inv_c)
-    # the roots sign(x) m {C, -P, -Q} about f, unsorted; mu_3 is the middle one
+    # the roots sign(x) m {C, -P, -Q} about f, unsorted (the sums are symmetric in the labels)
     mu1 = fmaf(ms, C, f)
     mu2 = fmaf(-ms, fmaf(np.full_like(C, f32(0.5)), C, rr), f)
     aa = np.abs(xc)
     ser = mul(aa, fmaf(mul(aa, aa), np.full_like(aa, f32(4 / 81)), f32(1 / 3)))
     Q = np.where(aa < f32(1 / 64), ser, fmaf(np.full_like(C, f32(0.5)), C, -rr)).astype(np.float32)
     mu3 = fmaf(-ms, Q, f)
+    g21 = mul(-ms, fmaf(np.full_like(C, f32(1.5)), C, rr))
     g31 = mul(-ms, add(C, Q))
     g32 = mul(mul(f32(2), ms), rr)
     inv_gp = mul(mul(np.copysign(f32(2.59807621135331594029), xc).astype(np.float32), r13), inv_y)
@@ -116,35 +114,29 @@ def node_terms(h, q, dh, dq, eta, w, g, kqg, band, sums):
     nF2 = -Fr2
     A1n = fmaf(nF2, dh, fmaf(mul(f32(2), Fr), dqn, eta))
     A2n = mul(b, fmaf(-Fr, dh, dqn))
-    up = mu3 >= 0
-    two = up == (ms >= 0)
-    mo = np.where(two, mu2, mu1).astype(np.float32)
-    mx = np.where(two, mu1, mu2).astype(np.float32)
-    gd = np.where(two, -g31, g32).astype(np.float32)
-    to = np.minimum(np.where(up, mo, -mo), f32(0)).astype(np.float32)
-    no = fmaf(fmaf(mu3, mx, nF2), dh, fmaf(mo, dqn, eta))
-    bo = mul(no, mul(to, gd))
-    eo = add(Fr, -mo)
-    wc = mul(wf, c)
+    n1 = fmaf(fmaf(mu2, mu3, nF2), dh, fmaf(mu1, dqn, eta))
+    n2 = fmaf(fmaf(mu3, mu1, nF2), dh, fmaf(mu2, dqn, eta))
+    n3 = fmaf(fmaf(mu1, mu2, nF2), dh, fmaf(mu3, dqn, eta))
+    b1 = mul(n1, mul(np.abs(mu1), g32))
+    b2 = mul(-n2, mul(np.abs(mu2), g31))
+    b3 = mul(n3, mul(np.abs(mu3), g21))
+    e1, e2, e3 = add(Fr, -mu1), add(Fr, -mu2), add(Fr, -mu3)
+    B0 = add(add(b1, b2), b3)
+    B1 = fmaf(b1, mu1, fmaf(b2, mu2, mul(b3, mu3)))
+    B2 = fmaf(b1, fmaf(e1, e1, f32(-1)), fmaf(b2, fmaf(e2, e2, f32(-1)), mul(b3, fmaf(e3, e3, f32(-1)))))
+    wc = mul(w, c)
     wcc = mul(wc, c)
-    pb = mul(mul(wc, inv_gp), bo)
-    S1, S2, SD = sums["S1"], sums["S2"], sums["SD"]
-    SD[0] = add(SD[0], pb)
-    SD[1] = fmaf(pb, mul(c, mo), SD[1])
-    SD[2] = fmaf(pb, fmaf(eo, eo, f32(-1)), SD[2])
-    a1 = fmaf(wcc, A1n, np.where(up, S1[0], S2[0]).astype(np.float32))
-    a2 = fmaf(wc, A2n, np.where(up, S1[1], S2[1]).astype(np.float32))
-    S1[0], S1[1] = np.where(up, a1, S1[0]).astype(np.float32), np.where(up, a2, S1[1]).astype(np.float32)
-    S2[0], S2[1] = np.where(up, S2[0], a1).astype(np.float32), np.where(up, S2[1], a2).astype(np.float32)
-    sums["Wt"] = np.where(up, sums["Wt"], sums["Wt"] + np.float64(w))
-    return inband
+    wcP, wccP = mul(wc, inv_gp), mul(wcc, inv_gp)
+    SA = (mul(wcc, A1n), mul(wc, A2n))
+    SB = (mul(wcP, B0), mul(wccP, B1), mul(wcP, B2))
+    return SA, SB, inband
 
 
 def fluct_fp32(WL, WR, g, xi, Ag, G=3, band=0.0):
     """D-, D+ ([3, n], float64) of the mixed form with every node in FP32 (no FP64 band): the
-    jumps and the free-surface jump formed in FP64 and rounded once, the node sums in FP32, and
-    D-, D+ formed from them in FP64 with row 0 of sum w A dW taken as dq.  Also returns, per edge,
-    whether any node's arccos argument lies within `band` of +-1."""
+    jumps and the free-surface jump formed in FP64 and rounded once, the h-row of sum w A dW
+    taken as dq, the node sums in FP32, D+- formed in FP64.  Also returns, per edge, whether any
+    node's arccos argument lies within `band` of +-1."""
     hL, qL, zL = (np.asarray(a, dtype=np.float64) for a in WL)
     hR, qR, zR = (np.asarray(a, dtype=np.float64) for a in WR)
     dh, dq, dz = hR - hL, qR - qL, zR - zL
@@ -152,20 +144,18 @@ def fluct_fp32(WL, WR, g, xi, Ag, G=3, band=0.0):
     x, wq = np.polynomial.legendre.leggauss(G)
     s, w = (x + 1) / 2, wq / 2
     kqg = 3.0 * xi * Ag * g
-    z32 = lambda: np.zeros(hL.shape, np.float32)
-    sums = {"S1": [z32(), z32()], "S2": [z32(), z32()], "SD": [z32(), z32(), z32()],
-            "Wt": np.zeros(hL.shape)}
+    SA = [np.zeros(hL.shape, np.float32) for _ in range(2)]
+    SB = [np.zeros(hL.shape, np.float32) for _ in range(3)]
     touched = np.zeros(hL.shape, dtype=bool)
     dhf, dqf = _r(dh), _r(dq)
     for k in range(G):
         sf = f32(s[k])
         hn = fmaf(np.full_like(dhf, sf), dhf, _r(hL))
         qn = fmaf(np.full_like(dqf, sf), dqf, _r(qL))
-        touched |= node_terms(hn, qn, dhf, dqf, eta, w[k], g, kqg, band, sums)
-    S1 = [v.astype(np.float64) for v in sums["S1"]]
-    S2 = [v.astype(np.float64) for v in sums["S2"]]
-    SD = [v.astype(np.float64) for v in sums["SD"]]
-    Dm0 = dq * sums["Wt"] + SD[0]
-    Dm = np.stack([Dm0, S2[0] + SD[1], S2[1] + SD[2]])
-    Dp = np.stack([dq - Dm0, S1[0] - SD[1], S1[1] - SD[2]])
-    return Dm, Dp, touched
+        sa, sb, inb = node_terms(hn, qn, dhf, dqf, eta, w[k], g, kqg, band)
+        touched |= inb
+        SA = [add(a, b) for a, b in zip(SA, sa)]
+        SB = [add(a, b) for a, b in zip(SB, sb)]
+    A = np.stack([dq, SA[0].astype(np.float64), SA[1].astype(np.float64)])
+    B = np.stack([v.astype(np.float64) for v in SB])
+    return 0.5 * (A - B), 0.5 * (A + B), touched
