@@ -44,6 +44,9 @@ HBM_PEAK_GBS = 8000.0
 # Launches chosen by the autotuner on an MI355X, keyed by device, precision, law and problem
 # shape; a hit sets the launch without trials (the profiles under profiles/ were taken at them)
 TUNE_CACHE = os.path.join(ROOT, "paper_1912_04791_amd", "tuned_launch.json")
+# Seconds of warm-up rounds before the timed steps of a workload timed beside the headline (its
+# timed region can be a fraction of a millisecond); the headline warms up for its W steps alone.
+EXTRA_WARM_S = 0.2
 
 # Algorithmic operation count of one edge update (each +, -, *, / and each sqrt, arccos,
 # cosine counted as one): the matrix-vector form of the DOT fluctuation costs about 150 flops,
@@ -217,18 +220,36 @@ def make_context(wl, precision: str, stream, launch=None, solver: str = "adot",
 
 
 def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: str = "adot",
-             tune_cache: str | None = TUNE_CACHE):
-    """W warm-up steps, then K steps timed with HIP events on the context's stream; the graphs
-    the timed run replays are captured before the timed region."""
+             tune_cache: str | None = TUNE_CACHE, warm_s: float = 0.0):
+    """W warm-up steps, then K steps timed with HIP events on the context's stream.  The graphs
+    of both runs are captured first, so the warm-up ends where the timed steps begin, with no
+    host wait between them.  With warm_s > 0 (the workloads timed beside the headline), rounds
+    of W warm-up steps run for warm_s seconds before that, so that a short timed region (20 c2
+    steps take 0.5 ms) starts at the clock the load holds rather than at an idle GPU's."""
     import torch
     stream = torch.cuda.current_stream()
     ctx, (h, q, z, t) = make_context(wl, precision, stream, launch, solver, tune_cache)
     if warmup > 0:
-        log_run(wl.name, precision, solver, warmup, "warmup")
-        ctx.adot_step(h, q, z, warmup, t)
+        ctx.prepare_run(h, q, z, warmup, t)
     ctx.prepare_run(h, q, z, steps, t)
     ctx.sync()
     torch.cuda.synchronize()
+    if warmup > 0:
+        if warm_s > 0:
+            # rounds of about 20 ms each, sized from one round of W steps
+            log_run(wl.name, precision, solver, warmup, "warmup")
+            t0 = time.perf_counter()
+            ctx.adot_step(h, q, z, warmup, t)
+            ctx.sync()
+            per_step = max((time.perf_counter() - t0) / warmup, 1e-6)
+            n_round = int(min(max(warmup, 0.02 / per_step), 5000))
+            t_end = time.perf_counter() + warm_s
+            while time.perf_counter() < t_end:
+                log_run(wl.name, precision, solver, n_round, "warmup")
+                ctx.adot_step(h, q, z, n_round, t)
+                ctx.sync()
+        log_run(wl.name, precision, solver, warmup, "warmup")
+        ctx.adot_step(h, q, z, warmup, t)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
@@ -448,13 +469,13 @@ def per_channel_l1(got, ref, sample) -> float:
     return worst
 
 
-def leg(wl, precisions, steps, warmup, launch, tune_cache):
+def leg(wl, precisions, steps, warmup, launch, tune_cache, warm_s: float = 0.0):
     """Timed runs of one workload in each precision, with their rooflines."""
     edges = wl.edges_per_step()
     ops = ops_per_edge_update(wl.n_gauss)
     out = {}
     for prec in precisions:
-        r = time_gpu(wl, prec, steps, warmup, launch, tune_cache=tune_cache)
+        r = time_gpu(wl, prec, steps, warmup, launch, tune_cache=tune_cache, warm_s=warm_s)
         v = edges * steps / (r["ms_total"] * 1e-3)
         msps = r["ms_total"] / steps
         print(f"[bench] {wl.name} {prec}: {msps * 1e3:.2f} us/step, {v:.4e} edge-updates/s",
@@ -471,6 +492,7 @@ def leg(wl, precisions, steps, warmup, launch, tune_cache):
             roof["note"] = ("ops count the scheme only; the closure's powers and roots per node "
                             "are extra work, so frac is a lower bound")
         out[prec] = {"value": v, "ms_per_step": msps, "steps": steps, "warmup": warmup,
+                     **({"warm_s": warm_s} if warm_s > 0 else {}),
                      "launch": {"tile": r["launch"][0], "blocks_per_cu": r["launch"][1],
                                 "graph_steps": r["launch"][2], "cfl_split": r["launch"][3]},
                      "graph": r["graph"], "roofline": roof}
@@ -573,7 +595,7 @@ def main():
 
     for name in extra:
         w2 = make_workload(name)
-        r2 = leg(w2, precisions, args.steps, args.warmup, launch, tune_cache)
+        r2 = leg(w2, precisions, args.steps, args.warmup, launch, tune_cache, warm_s=EXTRA_WARM_S)
         out[name] = {"workload": DESCRIPTIONS[w2.name], "n_cells": w2.n_cells,
                      "n_channels": w2.n_channels, "edges_per_step": w2.edges_per_step(), **r2}
         if len(precisions) > 1:
