@@ -436,8 +436,8 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
 enum { NODE_PER_LANE = 0, NODE_UP = 1, NODE_DOWN = 2 };
 
 // Sums over the nodes of an edge: S1, S2 = w A dW (rows 1, 2) over the nodes with mu_3 >= 0 and
-// mu_3 < 0, Wt = sum of w over the latter (row 0 of A dW is dq at every node), SD = the
-// projection terms of D^-.  Then D^- = (dq Wt, S2) + SD and D^+ = (dq, S1 + S2) - D^-; the
+// mu_3 < 0, Wt = sum of w over the latter (row 0 of A dW is dq at every node), SD = twice the
+// projection terms of D^-.  Then D^- = (dq Wt, S2) + SD/2 and D^+ = (dq, S1 + S2) - D^-; the
 // weights sum to one, so row 0 of S_A is dq.
 struct NodeSums {
     double S1[3], S2[3], SD[3];
@@ -463,14 +463,16 @@ __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh
     const double mo = two ? E.mu2 : E.mu1;
     const double mx = two ? E.mu1 : E.mu2;
     const double gd = two ? -E.g31 : E.g32;
-    // mu_o's share of D^-: min(mu_o, 0) when mu_3 >= 0, -max(mu_o, 0) otherwise
-    const double to = fmin(up ? mo : -mo, 0.0);
+    // twice mu_o's share of D^-: 2 min(mu_o, 0) = mu_o - |mu_o| when mu_3 >= 0, and
+    // -2 max(mu_o, 0) = -mu_o - |mu_o| otherwise (exact: a doubling or zero); the sums SD hold
+    // twice the projection terms
+    const double to = (up ? mo : -mo) - fabs(mo);
     // (l_o . dW) d_o P, non-dimensional: l_o = [1 - Fr^2 + mu_3 mu_x, mu_o, 1] (rows dh, dq/c, dz)
     const double no = fma(fma(E.mu3, mx, base), dh, fma(mo, dqn, dz));
     const double bo = no * (to * gd);
     const double eo = Fr - mo;
     const double wc = w * c, wcc = wc * c;
-    const double pb = (wc * E.inv_gp) * bo;   // w c to (l_o . dW): r_o = [1, c mu_o, (Fr - mu_o)^2 - 1]
+    const double pb = (wc * E.inv_gp) * bo;   // 2 w c mu_o^-+ (l_o . dW): r_o = [1, c mu_o, (Fr - mu_o)^2 - 1]
     N.SD[0] += pb;
     N.SD[1] = fma(pb, c * mo, N.SD[1]);
     N.SD[2] = fma(pb, fma(eo, eo, -1.0), N.SD[2]);
@@ -488,12 +490,12 @@ __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh
 __device__ __forceinline__ void node_sums_to_fluct(const NodeSums &N, double dq, double Dm[3],
                                                    double Dp[3])
 {
-    Dm[0] = fma(dq, N.Wt, N.SD[0]);
+    Dm[0] = fma(0.5, N.SD[0], dq * N.Wt);
     Dp[0] = dq - Dm[0];
 #pragma unroll
     for (int r = 1; r < 3; ++r) {
-        Dm[r] = N.S2[r] + N.SD[r];
-        Dp[r] = N.S1[r] - N.SD[r];
+        Dm[r] = fma(0.5, N.SD[r], N.S2[r]);
+        Dp[r] = fma(-0.5, N.SD[r], N.S1[r]);
     }
 }
 
@@ -513,9 +515,15 @@ __device__ __forceinline__ void fluct64(double hL, double qL, double zL, double 
         Eig64 E;
         eig64<CL>(fma(s, dh, hL), fma(s, dq, qL), g, K, E, xmax);
         const double w = Gauss<G>::w[k];
-        if (__all(E.mu3 >= 0.0 && E.ms >= 0.0)) node_minus64<NODE_UP>(E, w, dh, dq, dz, N);
-        else if (__all(E.mu3 < 0.0 && E.ms < 0.0)) node_minus64<NODE_DOWN>(E, w, dh, dq, dz, N);
-        else node_minus64<NODE_PER_LANE>(E, w, dh, dq, dz, N);
+        const unsigned long long act = __builtin_amdgcn_read_exec();
+        const unsigned long long m3 = __builtin_amdgcn_ballot_w64(E.mu3 >= 0.0);
+        const unsigned long long ms = __builtin_amdgcn_ballot_w64(E.ms >= 0.0);
+        if ((m3 & ms) == act)
+            node_minus64<NODE_UP>(E, w, dh, dq, dz, N);
+        else if ((m3 | ms) == 0ull)
+            node_minus64<NODE_DOWN>(E, w, dh, dq, dz, N);
+        else
+            node_minus64<NODE_PER_LANE>(E, w, dh, dq, dz, N);
     }
     bad |= arg_flags(xmax, true);
     node_sums_to_fluct(N, dq, Dm, Dp);
