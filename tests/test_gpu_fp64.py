@@ -78,6 +78,47 @@ def test_pairwise_fluct_matches_oracle(torch_dev, dsve, G):
     ctx.close()
 
 
+def test_node_paths_do_not_change_bits(torch_dev, dsve):
+    # An FP64 node takes a path chosen for its whole wave: flow towards +x in every lane, towards
+    # -x in every lane, or otherwise a per-lane choice of the eigenpair that D- is taken from
+    # (Sec. 3.1, Eqs. asbA, ExAbsA: one eigenvalue differs in sign from the middle one).  The
+    # same edges, laid out once in waves of one kind each and once shuffled (every wave mixed,
+    # some lanes past abs(Fr) = 3, where the eigenpair is the other one), must give the same
+    # bits edge by edge, and match the oracle.
+    torch = torch_dev
+    rng = np.random.default_rng(77)
+    n = 64 * 600
+    h = rng.uniform(0.3, 3.0, n)
+    hR = h * (1 + 0.05 * rng.uniform(-1, 1, n))
+    kind = np.arange(n) // (n // 3)            # 0: towards +x, 1: towards -x, 2: mixed signs and fast
+    fr = np.where(kind == 0, rng.uniform(0.05, 2.5, n),
+                  np.where(kind == 1, -rng.uniform(0.05, 2.5, n), rng.uniform(-5.0, 5.0, n)))
+    u = fr * np.sqrt(9.81 * h)
+    uR = u * (1 + 0.05 * rng.uniform(-1, 1, n))
+    z = rng.uniform(-0.2, 0.2, n)
+    zR = z + 0.02 * rng.uniform(-1, 1, n)
+    WL, WR = (h, h * u, z), (hR, hR * uR, zR)
+    perm = rng.permutation(n)
+    ctx = dsve.Context.single(16, porosity=0.4, A_g=0.01, dx=1.0)
+    outs = []
+    for order in (np.arange(n), perm):
+        dev = [torch.from_numpy(np.ascontiguousarray(a[order])).cuda() for a in (*WL, *WR)]
+        Dm = torch.zeros(3, n, dtype=torch.float64, device="cuda")
+        Dp = torch.zeros_like(Dm)
+        ctx.dot_edge_fluct(*dev, Dm, Dp)
+        ctx.sync()
+        gm, gp = np.empty((3, n)), np.empty((3, n))
+        gm[:, order], gp[:, order] = Dm.cpu().numpy(), Dp.cpu().numpy()
+        outs.append((gm, gp))
+    ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    rm, rp = oracle.fluct(WL, WR, 9.81, 1.0 / 0.6, 0.01)
+    sc = np.abs(rm).max(axis=0) + np.abs(rp).max(axis=0)
+    for got, ref in zip(outs[0], (rm, rp)):
+        per = np.abs(got - ref).max(axis=0) / sc
+        assert per.max() <= TOL, (per.max(), np.argmax(per))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("n", [0, 1, 63, 65, 257])
 def test_pairwise_fluct_small_and_ragged_edge_counts(torch_dev, dsve, n, precision):
