@@ -395,8 +395,9 @@ __device__ __forceinline__ double speed64(double h, double q, double g, const Cl
     return (a.gh * a.inv_c) * ((2.0 / 3.0) * fma(k1 * r1, cth, fabs(Fr)));
 }
 
-// Accumulate one quadrature node: SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node,
-// and the weights sum to one, so the caller takes sum_k w_k dq = dq), SB += w |A| dW.
+// One quadrature node with all three eigenpairs, for the mixed form's FP64 band nodes:
+// SA += w A dW (rows 1, 2; row 0 of A dW is dq at every node, and the weights sum to one, so the
+// caller takes sum_k w_k dq = dq), SB += w |A| dW.
 __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, double dh, double dq,
                                                   double dz, double SA[3], double SB[3])
 {
@@ -429,10 +430,11 @@ __device__ __forceinline__ void node_accumulate64(const Eig64 &E, double w, doub
     SB[2] = fma(wcP, B2, SB[2]);
 }
 
-// Paths of a quadrature node through D^-: with every lane's mu_3 >= 0 and ms >= 0 (flow towards
-// +x below |Fr| of about 3 under weak transport), o = 2 and D^- takes min(mu_2, 0); with every
-// lane's mu_3 < 0 and ms < 0 (the mirror case), o = 2 and D^- takes A dW - max(mu_2, 0); any
-// other wave picks o per lane (o = 2 exactly when the signs of mu_3 and ms agree).
+// Paths of an FP64 quadrature node through D^-: with every lane's mu_3 >= 0 and ms >= 0 (flow
+// towards +x below |Fr| of about 3 under weak transport), o = 2 and A^- dW takes the share
+// min(mu_2, 0) of that eigenpair; with every lane's mu_3 < 0 and ms < 0 (the mirror case), o = 2
+// and A^- dW = A dW less the share max(mu_2, 0); any other wave picks o per lane (o = 2 exactly
+// when the signs of mu_3 and ms agree).
 enum { NODE_PER_LANE = 0, NODE_UP = 1, NODE_DOWN = 2 };
 
 // Sums over the nodes of an edge: S1, S2 = w A dW (rows 1, 2) over the nodes with mu_3 >= 0 and
@@ -472,7 +474,8 @@ __device__ __forceinline__ void node_minus64(const Eig64 &E, double w, double dh
     const double bo = no * (to * gd);
     const double eo = Fr - mo;
     const double wc = w * c, wcc = wc * c;
-    const double pb = (wc * E.inv_gp) * bo;   // 2 w c mu_o^-+ (l_o . dW): r_o = [1, c mu_o, (Fr - mu_o)^2 - 1]
+    // w c to (l_o . dW), the weight of r_o = [1, c mu_o, (Fr - mu_o)^2 - 1] in 2 D^-
+    const double pb = (wc * E.inv_gp) * bo;
     N.SD[0] += pb;
     N.SD[1] = fma(pb, c * mo, N.SD[1]);
     N.SD[2] = fma(pb, fma(eo, eo, -1.0), N.SD[2]);
