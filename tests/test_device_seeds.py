@@ -292,3 +292,61 @@ def test_largest_speed_is_the_largest_root_at_abs_froude():
     m1, m2, m3 = roots(Fr)
     mx = np.maximum(np.maximum(np.abs(m1), np.abs(m2)), np.abs(m3))
     assert np.max(np.abs(mx - roots(np.abs(Fr))[2]) / mx) < 1e-14
+
+
+def test_one_eigenpair_minus_part_matches_lapack():
+    # The FP64 kernels take A^- dW = ((A - |A|)/2) dW (Sec. 3.1, Eqs. asbA, ExAbsA) from one
+    # eigenpair: mu_3 of the labelled roots is the middle one, so when mu_3 >= 0 only the
+    # smallest root o can be negative and A^- dW = c min(mu_o, 0) (l_o . dW) r_o, and when
+    # mu_3 < 0 only the largest can be positive and A^- dW = A dW - c max(mu_o, 0) (l_o . dW) r_o;
+    # o is labelled 2 when the signs of mu_3 and sign(x) m agree, else 1.  Checked against
+    # R min(Lambda, 0) R^-1 dW from LAPACK on the dimensional matrix of the Grass law.
+    rng = np.random.default_rng(42)
+    g, xi = 9.81, 1.0 / 0.6
+    n = 4000
+    h = rng.uniform(0.1, 3.0, n)
+    Fr_in = rng.uniform(-6.0, 6.0, n)
+    Ag = rng.choice([0.0, 1e-4, 1e-2, 5e-2], n)
+    c = np.sqrt(g * h)
+    u = Fr_in * c
+    dW = rng.standard_normal((n, 3)) * np.array([0.1, 0.1, 0.05])
+    kqg = 3 * xi * Ag * g
+    Fr = u / c
+    k1 = 3 + Fr ** 2 * (1 + 3 * kqg)
+    k2h = Fr * (9 - Fr ** 2 * (1 + 4.5 * kqg))
+    x = k2h / k1 ** 1.5
+    keep = 1 - np.abs(x) > 1e-3   # away from coalescing roots, where R^-1 is ill-conditioned
+    th = np.arccos(np.abs(x)) / 3
+    C, S = np.cos(th), np.sin(th)
+    ms = np.copysign(2.0 / 3.0 * np.sqrt(k1), x)
+    f = 2.0 / 3.0 * Fr
+    r = np.sqrt(3) / 2 * S
+    mu1, mu2, mu3 = f + ms * C, f - ms * (0.5 * C + r), f - ms * (0.5 * C - r)
+    mus = np.stack([mu1, mu2, mu3])
+    # mu_3 is the middle root
+    assert np.all(np.sort(mus, axis=0)[1] == mu3)
+    up = mu3 >= 0
+    two = up == (ms >= 0)
+    mo, mx = np.where(two, mu2, mu1), np.where(two, mu1, mu2)
+    # every other root has the sign of mu_3 (or is zero)
+    other = np.where(two, mu1, mu2)
+    assert np.all(np.where(up, other >= 0, other < 0) | (np.abs(other) < 1e-15))
+    no = (1 - Fr ** 2 + mu3 * mx) * dW[:, 0] + mo * dW[:, 1] / c + dW[:, 2]
+    lo = no / ((mo - mx) * (mo - mu3))
+    t = np.where(up, np.minimum(mo, 0), -np.maximum(mo, 0))
+    ro = np.stack([np.ones(n), c * mo, (Fr - mo) ** 2 - 1], axis=1)
+    A = np.zeros((n, 3, 3))
+    A[:, 0, 1] = 1
+    A[:, 1, 0], A[:, 1, 1], A[:, 1, 2] = c ** 2 - u ** 2, 2 * u, c ** 2
+    A[:, 2, 0], A[:, 2, 1] = xi * (-3 * Ag * u ** 3 / h), xi * (3 * Ag * u ** 2 / h)
+    AdW = np.einsum("nij,nj->ni", A, dW)
+    got = np.where(up[:, None], 0.0, AdW) + (c * t * lo)[:, None] * ro
+    lam, R = np.linalg.eig(A)
+    lam, R = lam.real, R.real
+    ref = np.einsum("nij,nj->ni", R * np.minimum(lam, 0)[:, None, :], np.linalg.solve(R, dW[..., None])[..., 0])
+    scale = np.abs(AdW).max(axis=1) + np.abs(ref).max(axis=1) + 1e-300
+    err = np.abs(got - ref).max(axis=1) / scale
+    assert keep.mean() > 0.9
+    assert err[keep].max() <= 1e-11, (err[keep].max(), np.argmax(np.where(keep, err, 0)))
+    # both cases and both labels occur
+    assert up[keep].any() and (~up[keep]).any() and two[keep].any() and (~two[keep]).any()
