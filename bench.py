@@ -223,9 +223,9 @@ def time_gpu(wl, precision: str, steps: int, warmup: int, launch=None, solver: s
              tune_cache: str | None = TUNE_CACHE, warm_s: float = 0.0):
     """W warm-up steps, then K steps timed with HIP events on the context's stream.  The graphs
     of both runs are captured first, so the warm-up ends where the timed steps begin, with no
-    host wait between them.  With warm_s > 0 (the workloads timed beside the headline), rounds
-    of W warm-up steps run for warm_s seconds before that, so that a short timed region (20 c2
-    steps take 0.5 ms) starts at the clock the load holds rather than at an idle GPU's."""
+    host wait between them.  With warm_s > 0 (the workloads timed beside the headline), warm-up
+    rounds of about 20 ms each run for warm_s seconds before that, so that a short timed region
+    (20 c2 steps take 0.5 ms) starts at the clock the load holds rather than at an idle GPU's."""
     import torch
     stream = torch.cuda.current_stream()
     ctx, (h, q, z, t) = make_context(wl, precision, stream, launch, solver, tune_cache)
