@@ -442,7 +442,7 @@ enum { NODE_PER_LANE = 0, NODE_UP = 1, NODE_DOWN = 2 };
 // projection terms of D^-.  Then D^- = (dq Wt, S2) + SD/2 and D^+ = (dq, S1 + S2) - D^-; the
 // weights sum to one, so row 0 of S_A is dq.
 struct NodeSums {
-    double S1[3], S2[3], SD[3];
+    double S1[3], S2[3], SD[3];   // rows 0-2 of the state; S1[0] and S2[0] are not used (dq, Wt)
     double Wt;
 };
 
