@@ -189,3 +189,22 @@ def test_profile_timing_note_wording():
     from paper_1912_04791_amd import profsum
     assert "below it" in profsum.timing_note(3500.0, 3400.0)
     assert "above it" in profsum.timing_note(27.0, 29.0)
+
+
+def test_relative_l1_floor_in_the_units_of_each_variable():
+    # bench.py and the tests measure parity the same way: per variable, relative to the
+    # reference's L1 norm or, where that is smaller, to a thousandth of the variable's natural
+    # size in its own units (the depth for h and z, the critical discharge h sqrt(g h) for q)
+    import numpy as np
+    sys.path.insert(0, os.path.dirname(__file__))
+    from common import max_rel_l1
+    rng = np.random.default_rng(3)
+    h = rng.uniform(0.5, 3.0, 500)
+    ref = (h, 1e-7 * rng.standard_normal(500), rng.uniform(-0.2, 0.2, 500))
+    got = tuple(r + 1e-9 * rng.standard_normal(500) for r in ref)
+    assert bench.rel_l1_max(got, ref) == max_rel_l1(got, ref)
+    # q is near zero everywhere: its floor is 1e-3 * sum(h sqrt(g h)), not its own norm
+    eq = np.abs(got[1] - ref[1]).sum() / (1e-3 * (h * np.sqrt(9.81 * h)).sum())
+    eh = np.abs(got[0] - ref[0]).sum() / np.abs(ref[0]).sum()
+    ez = np.abs(got[2] - ref[2]).sum() / max(np.abs(ref[2]).sum(), 1e-3 * h.sum())
+    assert bench.rel_l1_max(got, ref) == max(eh, eq, ez)

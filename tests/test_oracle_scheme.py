@@ -141,9 +141,10 @@ def test_adot_equals_numerical_eigensolver_dot(orc):
     hn, qn, zn, tn = dot_numeric.run(wl.h, wl.q, wl.z, wl.steps, wl.dx[0], wl.g, xi, wl.Ag[0],
                                      G=3, cfl=wl.cfl)
     assert abs(t - tn) <= 1e-12 * t
-    for a, r in ((h, hn), (q, qn), (z, zn)):
-        rel_l1 = np.abs(a - r).sum() / max(np.abs(r).sum(), 1e-3 * np.abs(hn).sum())
-        assert rel_l1 < 1e-12, rel_l1
+    from common import l1_scales, rel_l1
+    for a, r, sc in zip((h, q, z), (hn, qn, zn), l1_scales(hn)):
+        e = rel_l1(a, r, sc)
+        assert e < 1e-12, e
     assert np.max(np.abs(z - wl.z)) > 1e-4  # the bed moved
 
 
